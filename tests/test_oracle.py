@@ -1,0 +1,272 @@
+"""Pins of the CPU oracle against facts it does not compute itself:
+textbook sorting of python byte strings, brute force on tiny inputs, the
+paper's printed dataset statistics through closed forms, Fig. 1, and
+library routines for the single-step helpers."""
+import bisect
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_2056_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def brute(strs):
+    """Python's own ordering of bytes objects is the canonical lexicographic
+    order over unsigned bytes with a proper prefix first."""
+    perm = sorted(range(len(strs)), key=lambda i: (strs[i], i))
+    lcp = [0] * len(strs)
+    for i in range(1, len(strs)):
+        lcp[i] = len(os.path.commonprefix([strs[perm[i - 1]], strs[perm[i]]]))
+    return perm, lcp
+
+
+def run(strs, layout="csr", pad=0):
+    ss = W.from_list(strs, layout=layout, pad=pad)
+    perm, lcp = oracle.sort(ss)
+    return ss, list(perm), list(lcp)
+
+
+def test_exhaustive_tiny():
+    alphabet = [b""] + [bytes(p) for k in (1, 2, 3) for p in itertools.product(b"ab", repeat=k)]
+    assert len(alphabet) == 15
+    count = 0
+    for n in range(0, 4):
+        for combo in itertools.product(alphabet, repeat=n):
+            strs = list(combo)
+            ss, perm, lcp = run(strs)
+            assert (perm, lcp) == brute(strs), strs
+            assert oracle.check(ss, perm, lcp) == -1
+            count += 1
+    assert count == 1 + 15 + 225 + 3375
+
+
+def _adversarial(rng, n):
+    kind = rng.integers(0, 7)
+    if kind == 0:       # heavy duplicates over a tiny alphabet
+        pool = [bytes(rng.integers(97, 99, size=rng.integers(0, 6)).astype(np.uint8)) for _ in range(5)]
+        return [pool[rng.integers(0, 5)] for _ in range(n)]
+    if kind == 1:       # keys ending exactly at 8 / 16 bytes, shared prefixes
+        base = bytes(rng.integers(65, 91, size=24).astype(np.uint8))
+        return [base[: rng.choice([7, 8, 9, 15, 16, 17, 24])] + bytes([rng.integers(65, 68)]) * rng.integers(0, 2)
+                for _ in range(n)]
+    if kind == 2:       # extreme bytes 0x01 and 0xFF
+        return [bytes(rng.choice([1, 2, 254, 255], size=rng.integers(0, 12)).astype(np.uint8)) for _ in range(n)]
+    if kind == 3:       # prefix chains
+        s = bytes(rng.integers(97, 123, size=40).astype(np.uint8))
+        return [s[: rng.integers(0, 41)] for _ in range(n)]
+    if kind == 4:       # suffixes of a tiny periodic text
+        t = (b"abaab" * 20)[: rng.integers(1, 100)]
+        return [t[i:] for i in range(len(t))][:n]
+    if kind == 5:       # empty strings mixed in
+        return [b"" if rng.random() < 0.3 else bytes(rng.integers(33, 127, size=rng.integers(1, 30)).astype(np.uint8))
+                for _ in range(n)]
+    return [bytes(rng.integers(1, 256, size=rng.integers(0, 40)).astype(np.uint8)) for _ in range(n)]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_adversarial(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(0, 2000))
+    strs = _adversarial(rng, n)
+    layout = "lengths" if seed % 3 == 1 else "csr"
+    ss, perm, lcp = run(strs, layout=layout, pad=5 if layout == "lengths" else 0)
+    assert (perm, lcp) == brute(strs)
+    assert oracle.check(ss, perm, lcp) == -1
+
+
+def test_to_end_layout_suffixes():
+    text = W.suffix_text(3000, seed=9, block=256)
+    ss = W.StringSet(text, np.arange(len(text), dtype=np.uint64), None, W.FLAG_TO_END, len(text), {})
+    perm, lcp = oracle.sort(ss)
+    strs = [bytes(text[i:]) for i in range(len(text))]
+    bp, bl = brute(strs)
+    assert list(perm) == bp and list(lcp) == bl
+
+
+def test_generators_plain_against_brute():
+    ss = W.plain(3000, seed=11)
+    perm, lcp = oracle.sort(ss)
+    bp, bl = brute(ss.strings())
+    assert list(perm) == bp and list(lcp) == bl
+
+
+@pytest.mark.parametrize("planted", ["swap", "lcp_up", "lcp_down", "tie", "dup", "lcp0"])
+def test_checker_rejects_planted_mistakes(planted):
+    strs = [b"ab", b"abc", b"abc", b"b", b"ab", b"", b"abd", b"ba"]
+    ss, perm, lcp = run(strs)
+    perm, lcp = np.array(perm, dtype=np.uint32), np.array(lcp, dtype=np.uint32)
+    assert oracle.check(ss, perm, lcp) == -1
+    p, h = perm.copy(), lcp.copy()
+    if planted == "swap":
+        p[5], p[6] = p[6], p[5]
+    elif planted == "lcp_up":
+        h[3] += 1
+    elif planted == "lcp_down":
+        h[4] -= 1 if h[4] else 0
+        h[2] = max(int(h[2]) - 1, 0)
+    elif planted == "tie":      # identical strings out of index order
+        i = [k for k in range(1, len(p)) if strs[p[k]] == strs[p[k - 1]]][0]
+        p[i], p[i - 1] = p[i - 1], p[i]
+    elif planted == "dup":
+        p[1] = p[0]
+    elif planted == "lcp0":
+        h[0] = 1
+    assert oracle.check(ss, p, h) != -1
+
+
+# ---- closed forms for the paper's "Random" input and the DNA row ----
+
+def random_closed_form(n, sigma=94, lmax=20):
+    """Expected D/N (paper convention: one terminator per string) and L/n for
+    n strings with lengths uniform in [0,lmax) and i.i.d. uniform bytes.
+    A string of length l needs 1 + sum_{k<=l} P(M >= k) characters, M the
+    largest lcp with another string; sum_k H >= k counts, per depth k, the
+    strings of length >= k minus their distinct k-prefixes."""
+    e_dist = 0.0
+    for l in range(lmax):
+        s = 1.0
+        for k in range(1, l + 1):
+            pk = (lmax - k) / lmax * sigma ** (-k)
+            s += -math.expm1((n - 1) * math.log1p(-pk))
+        e_dist += s / lmax
+    dn = e_dist / ((lmax - 1) / 2 + 1)
+    ln = 0.0
+    for k in range(1, lmax):
+        P = (lmax - k) / lmax
+        pk = P * sigma ** (-k)
+        ln += P - sigma ** k * (-math.expm1(n * math.log1p(-pk))) / n
+    return dn, ln
+
+
+def fixed_len_closed_form(n, length, sigma):
+    e_dist = 1.0
+    ln = 0.0
+    for k in range(1, length + 1):
+        pk = sigma ** (-k)
+        e_dist += -math.expm1((n - 1) * math.log1p(-pk))
+        ln += 1 - sigma ** k * (-math.expm1(n * math.log1p(-pk))) / n
+    return e_dist / (length + 1), ln
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def test_closed_form_reproduces_paper_random_rows():
+    rows = _golden_rows("paper_random_dn.txt")
+    for r in rows:
+        if r[0] == "Ln":
+            dn, ln = random_closed_form(int(r[1]) / 10.5)
+            assert round(ln, 1) == float(r[2])
+        else:
+            dn, _ = random_closed_form(int(r[0]) / 10.5)
+            assert abs(100 * dn - float(r[1])) <= 0.05 + 1e-9, r
+
+
+def test_closed_form_reproduces_dna_row():
+    g = {r[0]: r[1] for r in _golden_rows("sinha_dna.txt")}
+    dn, ln = fixed_len_closed_form(int(g["n"]), int(g["len"]), int(g["sigma"]))
+    assert round(100 * dn) == int(g["D_over_N_percent"])
+    assert round(ln, 1) == float(g["L_over_n"])
+
+
+@pytest.mark.parametrize("n", [1 << 16, 1 << 20])
+def test_oracle_D_L_match_closed_form_random(n):
+    ss = W.paper_random(n, seed=21)
+    perm, lcp = oracle.sort(ss)
+    st = oracle.stats(ss, perm, lcp)
+    dn, ln = random_closed_form(n)
+    assert abs(st["D_paper"] / st["N_paper"] - dn) < 0.004
+    assert abs(st["L"] / n - ln) < 0.02
+    # the two D conventions differ exactly by the strings that need their terminator
+    assert st["D"] <= st["D_paper"] <= st["D"] + n
+    assert st["N_paper"] == st["N"] + n
+
+
+def test_oracle_D_L_match_closed_form_dna():
+    n, length = 1 << 18, 9
+    rng = np.random.default_rng(5)
+    chars = np.frombuffer(b"ACGT", dtype=np.uint8)[rng.integers(0, 4, size=n * length)]
+    off = np.arange(n + 1, dtype=np.uint64) * length
+    ss = W.StringSet(chars, off, None, 0, n, {})
+    perm, lcp = oracle.sort(ss)
+    st = oracle.stats(ss, perm, lcp)
+    dn, ln = fixed_len_closed_form(n, length, 4)
+    assert abs(st["D_paper"] / st["N_paper"] - dn) < 0.003
+    assert abs(st["L"] / n - ln) < 0.01
+
+
+# ---- single-step helpers ----
+
+def test_keys_big_endian_zero_padded():
+    strs = [b"", b"a", b"abcdefgh", b"abcdefghij", b"\xff\x01", b"xyz" * 5]
+    ss = W.from_list(strs)
+    for depth in (0, 1, 3, 8, 9, 20):
+        k = oracle.keys(ss, np.arange(len(strs)), depth)
+        for i, s in enumerate(strs):
+            ref = int.from_bytes((s[depth:depth + 8] + b"\0" * 8)[:8], "big")
+            assert int(k[i]) == ref
+
+
+def test_classify_is_lower_bound():
+    rng = np.random.default_rng(3)
+    for v in (1, 3, 7, 63, 255):
+        x = np.unique(rng.integers(0, 1000, size=v * 3).astype(np.uint64))[:v]
+        x.sort()
+        keys = np.concatenate([x, x + 1, rng.integers(0, 1100, size=500).astype(np.uint64)])
+        b = oracle.classify(keys, x)
+        xs = [int(t) for t in x]
+        for k, m in zip(keys, b):
+            l = bisect.bisect_left(xs, int(k))
+            assert m == 2 * l + (1 if l < len(xs) and xs[l] == int(k) else 0)
+
+
+def test_tree_fig1():
+    rows = {r[0]: r[1:] for r in _golden_rows("fig1_tree.txt")}
+    v = int(rows["v"][0])
+    assert list(oracle.tree_ranks(v)) == [int(t) for t in rows["level_order"]]
+    assert 2 * v + 1 == int(rows["buckets"][0])
+
+
+@pytest.mark.parametrize("d", range(1, 10))
+def test_tree_level_order_closed_form_and_inorder(d):
+    v = 2 ** d - 1
+    r = oracle.tree_ranks(v)
+    for j in range(1, v + 1):
+        delta = j.bit_length() - 1
+        p = j - 2 ** delta
+        assert r[j - 1] == (2 * p + 1) * 2 ** (d - 1 - delta) - 1
+    out = []
+
+    def inorder(j):
+        if j > v:
+            return
+        inorder(2 * j)
+        out.append(int(r[j - 1]))
+        inorder(2 * j + 1)
+    inorder(1)
+    assert out == list(range(v))
+
+
+def test_splitter_lcp_byte_loop():
+    rng = np.random.default_rng(4)
+    x = np.sort(rng.integers(0, 2**63, size=200, dtype=np.int64).astype(np.uint64))
+    x[50] = x[49]
+    x[60] = x[59] ^ np.uint64(1)
+    h = oracle.splitter_lcp(x)
+    assert h[0] == 0 and h[len(x)] == 0
+    for i in range(1, len(x)):
+        a, b = int(x[i - 1]).to_bytes(8, "big"), int(x[i]).to_bytes(8, "big")
+        assert h[i] == len(os.path.commonprefix([a, b]))
