@@ -1,0 +1,174 @@
+/*
+ * ssort.h: C ABI of libssort.so, a string sorter for one AMD Instinct MI355X
+ * (gfx950) built on parallel super scalar string sample sort.
+ *
+ * Problem (Preliminaries): n strings of total length N over an alphabet that
+ * excludes the zero byte; sort them lexicographically (unsigned bytes, a
+ * proper prefix before its extensions) and return the sorted order together
+ * with the LCP array H, H[0] = 0 and H[i] = lcp(s_perm[i-1], s_perm[i]).
+ * Identical strings appear in ascending input index, so the result is unique.
+ *
+ * Conventions for every call below:
+ *  - "device pointer" means memory of the context's GPU (hipMalloc or a torch
+ *    CUDA tensor); "host pointer" means ordinary process memory.
+ *  - The caller owns every buffer.  No call allocates device memory except
+ *    ssort_create / ssort_batch_graph_create / ssort_server_create.
+ *  - Sorting calls are asynchronous: they only enqueue work on `stream` (a
+ *    hipStream_t, or NULL for the default stream) and return.  Outputs are valid
+ *    once the stream has been synchronised.  They do not synchronise and do not
+ *    allocate, so they can be captured into a HIP graph.
+ *  - Host-checkable errors (null pointers, sizes, a workspace that is too
+ *    small, an invalid tuning) are returned synchronously and nothing is
+ *    enqueued.  Errors found on the device (a work-queue wait that exceeded its
+ *    time limit, a zero byte or an out-of-range string under SSORT_VALIDATE) are
+ *    reported by ssort_query_error after the stream has been synchronised; the
+ *    outputs are undefined then.
+ *  - A context may be used by one host thread at a time.  Sorts enqueued on
+ *    different streams with the same context must use different workspaces.
+ */
+#ifndef SSORT_H
+#define SSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSORT_OK = 0,
+    SSORT_EINVAL = 1,      /* bad argument */
+    SSORT_ENOMEM = 2,      /* allocation failed (create calls only) */
+    SSORT_EWORKSPACE = 3,  /* workspace smaller than ssort_workspace_bytes */
+    SSORT_EBOUNDS = 4,     /* device: a string lies outside the character buffer */
+    SSORT_EZEROBYTE = 5,   /* device: a string contains the byte 0 */
+    SSORT_EDEVICE = 6,     /* HIP runtime error */
+    SSORT_EBUSY = 7,       /* serving: job larger than the whole memory budget */
+    SSORT_ETIMEOUT = 8,    /* device: a work-queue wait exceeded its time limit */
+    SSORT_ENOTFOUND = 9    /* serving: unknown ticket */
+} ssort_status;
+
+/* flags of ssort_strings */
+#define SSORT_TO_END 1u    /* string i runs from offsets[i] to the end of chars (suffixes) */
+
+/* Input string set (a host struct holding device pointers).
+ *  chars    device, nchars bytes, any alignment; never read outside [0, nchars).
+ *  offsets  device uint64: n+1 CSR offsets (string i = chars[offsets[i], offsets[i+1]))
+ *           when lengths is NULL and SSORT_TO_END is not set; else n start offsets.
+ *  lengths  device uint32[n] or NULL.
+ *  n        number of strings, n <= 2^32 - 2.
+ * Every string must be shorter than 2^31 bytes and must not contain the byte 0
+ * (the terminator is outside the alphabet, Preliminaries). */
+typedef struct {
+    const uint8_t *chars;
+    uint64_t nchars;
+    const uint64_t *offsets;
+    const uint32_t *lengths;
+    uint32_t n;
+    uint32_t flags;
+} ssort_strings;
+
+/* Tuning of one context.
+ *  v               splitters per classification step, 2^d - 1 with d in 1..8
+ *                  (63, 127 or 255 in practice; the tree and its 2v+1 bucket
+ *                  counters live in LDS).  Algorithm 1; tree size choice in the
+ *                  implementation details of S5.
+ *  keys_per_thread keys each thread classifies at a time: 4 or 8.
+ *  base_threshold  segments of at most this many strings go to the LCP-aware
+ *                  base case (64..1024).
+ *  flags           SSORT_VALIDATE: check strings for bounds and zero bytes
+ *                  first (one extra pass over the characters). */
+typedef struct {
+    uint32_t v;
+    uint32_t keys_per_thread;
+    uint32_t base_threshold;
+    uint32_t flags;
+} ssort_tuning;
+
+#define SSORT_VALIDATE 1u
+
+typedef struct ssort_ctx ssort_ctx;
+
+/* Counters of the last sort (filled on the device, read after a sync).
+ *  segments     classification steps run (one per segment of > base_threshold strings)
+ *  strings      sum over those steps of their sizes (the active strings per level)
+ *  base_groups  groups handled by the base case
+ *  max_depth    largest depth (bytes) at which a step or base-case round ran */
+typedef struct {
+    uint64_t segments;
+    uint64_t strings;
+    uint64_t base_groups;
+    uint64_t max_depth;
+} ssort_stats_t;
+
+/* Create a context on HIP device `device` (the current device if < 0).
+ * t may be NULL for the default tuning.  Allocates a small control block on
+ * the device.  Returns SSORT_EINVAL for an invalid tuning. */
+ssort_status ssort_create(int device, const ssort_tuning *t, ssort_ctx **out);
+void ssort_destroy(ssort_ctx *ctx);
+ssort_status ssort_get_tuning(const ssort_ctx *ctx, ssort_tuning *t);
+
+/* Bytes of device workspace ssort_sort needs for n strings (m sets for the
+ * batched call; m = 1 for a plain sort). */
+ssort_status ssort_workspace_bytes(const ssort_ctx *ctx, uint32_t n, uint32_t m, size_t *bytes);
+
+/* Sort one string set (Algorithm 1 applied recursively, parallel S5).
+ *  out_perm  device uint32[n]: input index of the i-th smallest string.
+ *  out_lcp   device uint32[n] or NULL: the LCP array, out_lcp[0] = 0.
+ *  ws        device workspace of at least ssort_workspace_bytes(ctx, n, 1) bytes.
+ * n = 0 enqueues nothing. */
+ssort_status ssort_sort(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_perm,
+                        uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream);
+
+/* Sort m independent sets in one launch sequence.  The strings of all sets
+ * form one string space `flat`; set s is strings [set_begin[s], set_begin[s+1]).
+ *  set_begin  device uint32[m+1], non-decreasing, set_begin[m] = flat->n.
+ *  out_perm   device uint32[flat->n]: per set, set-local indices (0-based) in
+ *             sorted order, stored at the set's positions.
+ *  out_lcp    device uint32[flat->n] or NULL: per-set LCP arrays, 0 at each
+ *             set's first position.
+ *  ws         at least ssort_workspace_bytes(ctx, flat->n, m) bytes. */
+ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const uint32_t *set_begin,
+                                uint32_t m, uint32_t *out_perm, uint32_t *out_lcp, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* Device-side errors of the last sort enqueued with this context; call after
+ * synchronising its stream.  Resets the error word. */
+ssort_status ssort_query_error(ssort_ctx *ctx, void *stream);
+
+/* Counters of the last sort with this context (after synchronising). */
+ssort_status ssort_stats(ssort_ctx *ctx, ssort_stats_t *out, void *stream);
+
+/* Time limit of each work-queue wait, in milliseconds (default 20000).  A wait
+ * beyond it ends the sort with SSORT_ETIMEOUT instead of hanging. */
+ssort_status ssort_set_wait_limit(ssort_ctx *ctx, uint32_t ms);
+
+/* Device facts the context runs with: out[0] compute units, out[1] resident
+ * persistent workgroups (units x occupancy), out[2] wall-clock rate in kHz
+ * used for wait limits, out[3] HIP device index.  Host pointer, 4 entries. */
+ssort_status ssort_device_info(const ssort_ctx *ctx, uint64_t *out);
+
+const char *ssort_strerror(ssort_status s);
+
+/* ---- one classification step with its intermediates (parity checks) ----
+ * Runs one step of Algorithm 1 over all n strings of `in` at common depth
+ * `depth` (the caller guarantees the strings share that prefix), on the input
+ * order, with the library's own sample and splitters.  Outputs (device):
+ *  keys      uint64[n]   8-byte big-endian keys at `depth` (zero past the end)
+ *  split     uint64[256] sorted splitters x_0..x_{v'-1} actually used
+ *  tree      uint64[256] level-order tree, tree[j-1] = node j
+ *  info      uint32[4]   {v', d', number of distinct sample keys, 0}
+ *  bucket    uint16[n]   bucket of each string, 0..2v'
+ *  hist      uint32[512] strings per bucket
+ *  perm      uint32[n]   input indices after the stable redistribution
+ * ws as for ssort_sort with n strings. */
+ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t depth,
+                              uint64_t *keys, uint64_t *split, uint64_t *tree, uint32_t *info,
+                              uint16_t *bucket, uint32_t *hist, uint32_t *perm, void *ws,
+                              size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSORT_H */

@@ -1,0 +1,341 @@
+// Host side of libssort.so: the C ABI declared in include/ssort.h.
+// One translation unit with the kernels so that every template instance the
+// host launches is compiled here.
+#include <hip/hip_runtime.h>
+#include <stdlib.h>
+#include <string.h>
+#include <algorithm>
+
+#include "ssort.h"
+#include "ssort_kernels.hip"
+
+using namespace ssd;
+
+struct ssort_ctx {
+    int device;
+    ssort_tuning tun;
+    int cus;
+    int worker_blocks;
+    unsigned long long wall_khz;
+    uint32_t wait_ms;
+    void *last_ws;
+};
+
+namespace {
+
+constexpr uint32_t ROOT_MULTI_MIN = 1u << 16;   // whole-GPU root step above this size
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+uint64_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+struct Layout {
+    size_t ctl, r0, r1, bkt, ring, split, hist, totals, total;
+    uint64_t cap;
+    uint32_t ntiles;
+};
+
+Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
+    Layout L;
+    const uint32_t K = c->tun.keys_per_thread;
+    L.ntiles = n ? (uint32_t)((n + (uint64_t)NT * K - 1) / ((uint64_t)NT * K)) : 0u;
+    // queued tasks are disjoint segments of more than base_threshold strings
+    // plus the root tasks; twice that bound leaves every slot's previous
+    // occupant consumed long before the slot is reused
+    const uint64_t live = (uint64_t)n / (c->tun.base_threshold + 1) + m + NBMAX + (uint64_t)c->worker_blocks;
+    L.cap = next_pow2(2 * live + 1024);
+    size_t off = 0;
+    L.ctl = off;
+    off = align_up(off + sizeof(Ctl), 256);
+    L.r0 = off;
+    off = align_up(off + sizeof(Rec) * (size_t)n, 256);
+    L.r1 = off;
+    off = align_up(off + sizeof(Rec) * (size_t)n, 256);
+    L.bkt = off;
+    off = align_up(off + 2 * (size_t)n, 256);
+    L.ring = off;
+    off = align_up(off + sizeof(Slot) * (size_t)L.cap, 256);
+    L.split = off;
+    off = align_up(off + sizeof(Split), 256);
+    L.hist = off;
+    off = align_up(off + 4 * (size_t)NBPAD * L.ntiles, 256);
+    L.totals = off;
+    off = align_up(off + 4 * (size_t)NBPAD, 256);
+    L.total = off;
+    return L;
+}
+
+bool valid_tuning(const ssort_tuning &t) {
+    const uint32_t v = t.v;
+    if (v < 1 || v > VMAX || ((v + 1) & v) != 0) return false;
+    if (t.keys_per_thread != 4 && t.keys_per_thread != 8) return false;
+    if (t.base_threshold < 16 || t.base_threshold > (uint32_t)CH) return false;
+    return true;
+}
+
+int chunk_for(uint32_t tbase) { return tbase <= 256 ? 512 : 1024; }
+
+template <int K, int C>
+hipError_t worker_occupancy(int *nb) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, (const void *)k_worker<K, C>, NT, 0);
+}
+
+hipError_t occupancy(const ssort_tuning &t, int *nb) {
+    const int C = chunk_for(t.base_threshold);
+    if (t.keys_per_thread == 4) return C == 512 ? worker_occupancy<4, 512>(nb) : worker_occupancy<4, 1024>(nb);
+    return C == 512 ? worker_occupancy<8, 512>(nb) : worker_occupancy<8, 1024>(nb);
+}
+
+// Persistent workers: as many as fit on the GPU, but no more than the work
+// can use (about one per 512 strings, at least one per root task).
+uint32_t worker_grid(const ssort_ctx *c, uint64_t n, uint64_t roots) {
+    uint64_t want = std::max<uint64_t>((n + 511) / 512, roots);
+    want = std::max<uint64_t>(want, 1);
+    return (uint32_t)std::min<uint64_t>(want, (uint64_t)c->worker_blocks);
+}
+
+void launch_worker(const ssort_ctx *c, const Params &P, uint32_t grid, hipStream_t s) {
+    const int C = chunk_for(c->tun.base_threshold);
+    const dim3 g(grid), b(NT);
+    if (c->tun.keys_per_thread == 4) {
+        if (C == 512) hipLaunchKernelGGL((k_worker<4, 512>), g, b, 0, s, P);
+        else hipLaunchKernelGGL((k_worker<4, 1024>), g, b, 0, s, P);
+    } else {
+        if (C == 512) hipLaunchKernelGGL((k_worker<8, 512>), g, b, 0, s, P);
+        else hipLaunchKernelGGL((k_worker<8, 1024>), g, b, 0, s, P);
+    }
+}
+
+void launch_root(const ssort_ctx *c, const Params &P, uint32_t ntiles, uint32_t depth, bool schedule,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_root_sample, dim3(1), dim3(NT), 0, s, P, depth);
+    if (c->tun.keys_per_thread == 4) hipLaunchKernelGGL((k_root_classify<4>), dim3(ntiles), dim3(NT), 0, s, P, depth);
+    else hipLaunchKernelGGL((k_root_classify<8>), dim3(ntiles), dim3(NT), 0, s, P, depth);
+    hipLaunchKernelGGL(k_root_colscan, dim3(NBMAX), dim3(NT), 0, s, P);
+    if (c->tun.keys_per_thread == 4) hipLaunchKernelGGL((k_root_scatter<4>), dim3(ntiles), dim3(NT), 0, s, P);
+    else hipLaunchKernelGGL((k_root_scatter<8>), dim3(ntiles), dim3(NT), 0, s, P);
+    if (schedule) hipLaunchKernelGGL(k_root_schedule, dim3(1), dim3(NT), 0, s, P, depth);
+}
+
+ssort_status check_strings(const ssort_strings *in) {
+    if (!in) return SSORT_EINVAL;
+    if (in->n == 0) return SSORT_OK;
+    if (in->n > 0xFFFFFFFEu || !in->offsets) return SSORT_EINVAL;
+    if (!in->chars && in->nchars) return SSORT_EINVAL;
+    if ((in->flags & SSORT_TO_END) && in->nchars >= 0x80000000ull) return SSORT_EINVAL;
+    if (in->flags & ~SSORT_TO_END) return SSORT_EINVAL;
+    return SSORT_OK;
+}
+
+Params make_params(const ssort_ctx *c, const ssort_strings *in, uint32_t *perm, uint32_t *lcp, void *ws,
+                   const Layout &L, uint32_t m, const uint32_t *set_begin) {
+    Params P;
+    memset(&P, 0, sizeof(P));
+    P.S.chars = in->chars;
+    P.S.nchars = in->nchars;
+    P.S.off = in->offsets;
+    P.S.len = in->lengths;
+    P.S.n = in->n;
+    P.S.flags = in->flags;
+    char *w = (char *)ws;
+    P.R0 = (Rec *)(w + L.r0);
+    P.R1 = (Rec *)(w + L.r1);
+    P.bkt = (uint16_t *)(w + L.bkt);
+    P.perm = perm;
+    P.lcp = lcp;
+    P.ring = (Slot *)(w + L.ring);
+    P.ring_mask = L.cap - 1;
+    P.ctl = (Ctl *)(w + L.ctl);
+    P.gsplit = (Split *)(w + L.split);
+    P.hist = (uint32_t *)(w + L.hist);
+    P.totals = (uint32_t *)(w + L.totals);
+    P.set_begin = set_begin;
+    P.m = m;
+    P.ntiles = L.ntiles;
+    P.tbase = c->tun.base_threshold;
+    P.vmax = c->tun.v;
+    P.limit_ticks = (unsigned long long)c->wait_ms * c->wall_khz;
+    P.limit_iters = (unsigned long long)c->wait_ms * 2000ull;   // polls take well over 0.5 us each
+    return P;
+}
+
+uint32_t grid_for(uint64_t work) {
+    uint64_t g = (work + NT - 1) / NT;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (uint32_t)g;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ssort_strerror(ssort_status s) {
+    switch (s) {
+    case SSORT_OK: return "ok";
+    case SSORT_EINVAL: return "invalid argument";
+    case SSORT_ENOMEM: return "out of memory";
+    case SSORT_EWORKSPACE: return "workspace too small";
+    case SSORT_EBOUNDS: return "string outside the character buffer";
+    case SSORT_EZEROBYTE: return "string contains a zero byte";
+    case SSORT_EDEVICE: return "HIP runtime error";
+    case SSORT_EBUSY: return "job larger than the memory budget";
+    case SSORT_ETIMEOUT: return "device work-queue wait timed out";
+    case SSORT_ENOTFOUND: return "unknown ticket";
+    }
+    return "unknown status";
+}
+
+ssort_status ssort_create(int device, const ssort_tuning *t, ssort_ctx **out) {
+    if (!out) return SSORT_EINVAL;
+    *out = nullptr;
+    ssort_tuning tun = t ? *t : ssort_tuning{255, 4, 128, 0};
+    if (!valid_tuning(tun)) return SSORT_EINVAL;
+    if (device < 0 && hipGetDevice(&device) != hipSuccess) return SSORT_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return SSORT_EDEVICE;
+    ssort_ctx *c = (ssort_ctx *)calloc(1, sizeof(ssort_ctx));
+    if (!c) return SSORT_ENOMEM;
+    c->device = device;
+    c->tun = tun;
+    c->wait_ms = 20000;
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        free(c);
+        return SSORT_EDEVICE;
+    }
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0) khz = 100000;
+    c->wall_khz = (unsigned long long)khz;
+    int nb = 0;
+    if (occupancy(tun, &nb) != hipSuccess || nb < 1) nb = 1;
+    c->worker_blocks = c->cus * nb;
+    *out = c;
+    return SSORT_OK;
+}
+
+void ssort_destroy(ssort_ctx *ctx) { free(ctx); }
+
+ssort_status ssort_get_tuning(const ssort_ctx *ctx, ssort_tuning *t) {
+    if (!ctx || !t) return SSORT_EINVAL;
+    *t = ctx->tun;
+    return SSORT_OK;
+}
+
+ssort_status ssort_device_info(const ssort_ctx *ctx, uint64_t *out) {
+    if (!ctx || !out) return SSORT_EINVAL;
+    out[0] = (uint64_t)ctx->cus;
+    out[1] = (uint64_t)ctx->worker_blocks;
+    out[2] = ctx->wall_khz;
+    out[3] = (uint64_t)ctx->device;
+    return SSORT_OK;
+}
+
+ssort_status ssort_set_wait_limit(ssort_ctx *ctx, uint32_t ms) {
+    if (!ctx || ms == 0) return SSORT_EINVAL;
+    ctx->wait_ms = ms;
+    return SSORT_OK;
+}
+
+ssort_status ssort_workspace_bytes(const ssort_ctx *ctx, uint32_t n, uint32_t m, size_t *bytes) {
+    if (!ctx || !bytes || m == 0) return SSORT_EINVAL;
+    *bytes = layout(ctx, n, m).total;
+    return SSORT_OK;
+}
+
+ssort_status ssort_sort(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_perm, uint32_t *out_lcp, void *ws,
+                        size_t ws_bytes, void *stream) {
+    if (!ctx) return SSORT_EINVAL;
+    ssort_status st = check_strings(in);
+    if (st != SSORT_OK) return st;
+    if (in->n == 0) return SSORT_OK;
+    if (!out_perm || !ws) return SSORT_EINVAL;
+    const Layout L = layout(ctx, in->n, 1);
+    if (ws_bytes < L.total) return SSORT_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
+    Params P = make_params(ctx, in, out_perm, out_lcp, ws, L, 1, nullptr);
+    const bool multi = in->n > ROOT_MULTI_MIN;
+    hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, multi ? 0u : 1u,
+                       (unsigned long long)L.cap);
+    if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
+    if (multi) launch_root(ctx, P, L.ntiles, 0, true, s);
+    launch_worker(ctx, P, worker_grid(ctx, in->n, multi ? NBMAX : 1), s);
+    if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
+    ctx->last_ws = ws;
+    return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
+}
+
+ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const uint32_t *set_begin, uint32_t m,
+                                uint32_t *out_perm, uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream) {
+    if (!ctx || m == 0 || !set_begin) return SSORT_EINVAL;
+    ssort_status st = check_strings(flat);
+    if (st != SSORT_OK) return st;
+    if (flat->n == 0) return SSORT_OK;
+    if (!out_perm || !ws) return SSORT_EINVAL;
+    const Layout L = layout(ctx, flat->n, m);
+    if (ws_bytes < L.total) return SSORT_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
+    Params P = make_params(ctx, flat, out_perm, out_lcp, ws, L, m, set_begin);
+    hipLaunchKernelGGL(k_init, dim3(grid_for(std::max<uint64_t>(L.cap, m))), dim3(NT), 0, s, P, 2u,
+                       (unsigned long long)L.cap);
+    if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
+    launch_worker(ctx, P, worker_grid(ctx, flat->n, m), s);
+    if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
+    ctx->last_ws = ws;
+    return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
+}
+
+ssort_status ssort_query_error(ssort_ctx *ctx, void *stream) {
+    if (!ctx) return SSORT_EINVAL;
+    if (!ctx->last_ws) return SSORT_OK;
+    Ctl c;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&c, ctx->last_ws, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess) return SSORT_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return SSORT_EDEVICE;
+    if (c.error & ERR_BOUNDS) return SSORT_EBOUNDS;
+    if (c.error & ERR_ZERO) return SSORT_EZEROBYTE;
+    if (c.error & ERR_TIMEOUT) return SSORT_ETIMEOUT;
+    if (c.error) return SSORT_EDEVICE;
+    return SSORT_OK;
+}
+
+ssort_status ssort_stats(ssort_ctx *ctx, ssort_stats_t *out, void *stream) {
+    if (!ctx || !out) return SSORT_EINVAL;
+    memset(out, 0, sizeof(*out));
+    if (!ctx->last_ws) return SSORT_OK;
+    Ctl c;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&c, ctx->last_ws, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess) return SSORT_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return SSORT_EDEVICE;
+    out->segments = c.st_segments;
+    out->strings = c.st_strings;
+    out->base_groups = c.st_base;
+    out->max_depth = c.st_maxdepth;
+    return SSORT_OK;
+}
+
+ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t depth, uint64_t *keys, uint64_t *split,
+                              uint64_t *tree, uint32_t *info, uint16_t *bucket, uint32_t *hist, uint32_t *perm,
+                              void *ws, size_t ws_bytes, void *stream) {
+    if (!ctx) return SSORT_EINVAL;
+    ssort_status st = check_strings(in);
+    if (st != SSORT_OK) return st;
+    if (in->n == 0 || !keys || !split || !tree || !info || !bucket || !hist || !perm || !ws) return SSORT_EINVAL;
+    const Layout L = layout(ctx, in->n, 1);
+    if (ws_bytes < L.total) return SSORT_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
+    Params P = make_params(ctx, in, perm, nullptr, ws, L, 1, nullptr);
+    hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, 0u, (unsigned long long)L.cap);
+    launch_root(ctx, P, L.ntiles, depth, false, s);
+    hipLaunchKernelGGL(k_debug_dump, dim3(grid_for(in->n)), dim3(NT), 0, s, P, depth, keys, split, tree, info, bucket,
+                       hist, perm);
+    ctx->last_ws = ws;
+    return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
+}
+
+}  // extern "C"

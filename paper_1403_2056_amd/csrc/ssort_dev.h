@@ -1,0 +1,255 @@
+// Device-side building blocks of the string sample sorter (gfx950, wave64).
+//
+// Notation follows Algorithm 1 (one step of super scalar string sample sort):
+// a segment of strings with common prefix h is classified by the 8 characters
+// at depth h (w = 8), packed big-endian into one uint64 so that one unsigned
+// compare orders 8 characters; v = 2^d - 1 splitters x_0 < ... < x_{v-1} form
+// a perfect search tree held in LDS in level order; bucket 2l holds keys
+// strictly between x_{l-1} and x_l, bucket 2l+1 keys equal to x_l.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssd {
+
+constexpr int NT = 256;                 // threads per workgroup
+constexpr int NW = NT / 64;             // waves per workgroup
+constexpr int VMAX = 255;               // largest splitter count (d = 8)
+constexpr int DMAX = 8;
+constexpr int NBMAX = 2 * VMAX + 1;     // 511 buckets
+constexpr int NBPAD = 512;
+constexpr int SAMPLE_MAX = 2 * (VMAX + 1) - 1;   // oversampling factor 2
+constexpr int CH = 1024;                // base-case chunk (strings held in LDS)
+constexpr uint32_t SEAM = 0x80000000u;  // lcp slot still holds a separation depth
+constexpr uint32_t TO_END = 1u;
+
+// One string reference: start offset, length, input index.
+struct __align__(16) Rec {
+    uint64_t st;
+    uint32_t ln;
+    uint32_t id;
+};
+
+struct Strs {
+    const uint8_t *chars;
+    uint64_t nchars;
+    const uint64_t *off;
+    const uint32_t *len;
+    uint32_t n;
+    uint32_t flags;
+};
+
+__device__ __forceinline__ Rec make_rec(const Strs &S, uint32_t i) {
+    Rec r;
+    r.st = S.off[i];
+    r.id = i;
+    if (S.flags & TO_END) r.ln = (uint32_t)(S.nchars - r.st);
+    else if (S.len) r.ln = S.len[i];
+    else r.ln = (uint32_t)(S.off[i + 1] - r.st);
+    return r;
+}
+
+// The 8 characters of a string from depth h, first character in the most
+// significant byte, zero past the end of the string (the zero terminator is
+// outside the alphabet, so the padding orders a proper prefix first).  Reads
+// only the aligned 8-byte words that hold at least one byte of the string.
+__device__ __forceinline__ uint64_t key_at(const uint8_t *chars, uint64_t nchars, uint64_t st, uint32_t ln,
+                                           uint32_t h) {
+    if (h >= ln) return 0;
+    const uint64_t p = st + h;
+    if (p >= nchars) return 0;   // never read outside the buffer (valid inputs never get here)
+    const uint32_t rem = (uint32_t)min((uint64_t)(ln - h), nchars - p);
+    const uintptr_t a = (uintptr_t)(chars + p);
+    const uintptr_t a0 = a & ~(uintptr_t)7;
+    const uint32_t sh = (uint32_t)(a & 7);
+    uint64_t w = *(const uint64_t *)a0 >> (8 * sh);
+    if (sh != 0 && rem > 8 - sh) w |= *(const uint64_t *)(a0 + 8) << (64 - 8 * sh);
+    uint64_t k = __builtin_bswap64(w);
+    if (rem < 8) k &= ~0ull << (8 * (8 - rem));
+    return k;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Broadcast a value that is equal in every thread (read from LDS after a
+// barrier) so that the compiler treats it as uniform.  Every branch or loop
+// that contains a barrier must be controlled by such values: with a
+// condition the compiler cannot prove uniform it may lower the region as an
+// exec-masked divergent loop, where the lanes of one wave no longer reach a
+// barrier together.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Lanes of the wave holding the same bucket number (wave64 has no match
+// instruction: one ballot per bit of the bucket number).
+__device__ __forceinline__ uint64_t match_any(uint32_t m, int nbits) {
+    uint64_t mask = ~0ull;
+#pragma unroll 1
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (m >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        mask &= bit ? bal : ~bal;
+    }
+    return mask;
+}
+
+// Inclusive scan within a wave.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_incl_scan(T x, Op op) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (l >= (uint32_t)o) x = op(x, y);
+    }
+    return x;
+}
+
+struct AddOp { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; } };
+struct MaxOp { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; } };
+
+// Exclusive (or inclusive) scan of a[0..len) in LDS by the whole workgroup;
+// each thread owns a run of consecutive entries.  tmp needs NW entries.
+// Returns the total.  Must be called by all threads; includes barriers.
+template <typename Op>
+__device__ uint32_t block_scan(uint32_t *a, int len, uint32_t *tmp, bool exclusive, Op op, uint32_t ident) {
+    const int tid = threadIdx.x;
+    const int per = (len + NT - 1) / NT;
+    const int lo = tid * per;
+    const int hi = min(len, lo + per);
+    uint32_t acc = ident;
+    for (int i = lo; i < hi; ++i) acc = op(acc, a[i]);
+    uint32_t inc = wave_incl_scan(acc, op);
+    const int w = tid >> 6;
+    if ((tid & 63) == 63) tmp[w] = inc;
+    __syncthreads();
+    uint32_t wpre = ident;
+    for (int j = 0; j < w; ++j) wpre = op(wpre, tmp[j]);
+    uint32_t total = ident;
+    for (int j = 0; j < NW; ++j) total = op(total, tmp[j]);
+    total = uni(total);
+    uint32_t run = op(wpre, __shfl_up(inc, 1, 64));
+    if ((tid & 63) == 0) run = wpre;
+    for (int i = lo; i < hi; ++i) {
+        const uint32_t x = a[i];
+        const uint32_t nx = op(run, x);
+        a[i] = exclusive ? run : nx;
+        run = nx;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Splitter set of one classification step (LDS or global copy).
+struct Split {
+    uint64_t tree[VMAX + 1];   // level order, tree[1..v]
+    uint64_t x[VMAX + 1];      // in-order (sorted) splitters x[0..v)
+    uint8_t hl[VMAX + 1];      // hl[l] = lcp(x[l-1], x[l]) in bytes, hl[0] = hl[v] = 0
+    uint8_t zr[VMAX + 1];      // zr[l] = x[l] ends its string (last byte zero)
+    uint32_t v, d, nb, nbits, ndistinct, pad[3];
+};
+
+// Bucket of key c: descend the level-order tree going right when c > t_i,
+// then l = i - (v+1) counts the splitters below c; bucket 2l, plus one when
+// the key equals x_l (the last bucket 2v has no equality test).
+__device__ __forceinline__ uint32_t classify(uint64_t c, const Split &sp) {
+    uint32_t i = 1;
+#pragma unroll
+    for (int l = 0; l < DMAX; ++l)
+        if (l < (int)sp.d) i = 2 * i + (c > sp.tree[i] ? 1u : 0u);
+    const uint32_t l = i - (sp.v + 1);
+    return 2 * l + ((l < sp.v && sp.x[l] == c) ? 1u : 0u);
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+    x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+    return x;
+}
+
+// Sample keys and splitters for a segment of `size` strings at depth h, read
+// through `load(e)` (0 <= e < size).  Sample of up to 2(v+1)-1 keys (all
+// strings when the segment is that small, else one pseudo-random pick per
+// stratum), sorted in LDS by rank counting; the distinct sample keys become
+// the splitters when they fit into the tree (the smallest tree 2^d'-1 >= their
+// number, padded by the largest), else v equidistant distinct keys, so that no
+// splitter repeats (cf. the skip-duplicates selection).  Then the level-order
+// tree, the splitter LCPs (xor + count leading zeros) and the end-of-string
+// flags.  `samp`, `srt` need SAMPLE_MAX+1 entries, `fl` SAMPLE_MAX+1, tmp NW.
+template <typename Load>
+__device__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
+                                 uint64_t *samp, uint64_t *srt, uint32_t *fl, uint32_t *tmp, Load load) {
+    const int tid = threadIdx.x;
+    const uint32_t a = size < (uint32_t)(2 * (vmax + 1) - 1) ? size : (uint32_t)(2 * (vmax + 1) - 1);
+    const bool all = size <= a;
+    const uint32_t stride = all ? 1u : size / a;
+    for (uint32_t t = tid; t < a; t += NT) {
+        uint32_t pos;
+        if (all) pos = t;
+        else pos = (uint32_t)(((uint64_t)t * size) / a) + hash32(seed ^ (t * 0x9E3779B9u)) % stride;
+        samp[t] = load(pos, h);
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < a; t += NT) {
+        const uint64_t k = samp[t];
+        uint32_t r = 0;
+        for (uint32_t j = 0; j < a; ++j) {
+            const uint64_t q = samp[j];
+            r += (q < k || (q == k && j < t)) ? 1u : 0u;
+        }
+        srt[r] = k;
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < a; t += NT) fl[t] = (t == 0 || srt[t] != srt[t - 1]) ? 1u : 0u;
+    __syncthreads();
+    const uint32_t U = uni(block_scan(fl, (int)a, tmp, true, AddOp(), 0u));
+    // compact the distinct keys into samp[0..U)
+    for (uint32_t t = tid; t < a; t += NT)
+        if (t == 0 || srt[t] != srt[t - 1]) samp[fl[t]] = srt[t];
+    __syncthreads();
+    uint32_t d, v;
+    if (U <= vmax) {
+        d = 1;
+        while ((1u << d) - 1 < U) ++d;
+        v = (1u << d) - 1;
+    } else {
+        v = vmax;
+        d = 31 - __clz(vmax + 1);
+    }
+    for (uint32_t j = tid; j < v; j += NT) {
+        uint32_t src;
+        if (U <= vmax) src = j < U ? j : U - 1;
+        else src = (uint32_t)(((uint64_t)(j + 1) * U) / (v + 1));
+        sp.x[j] = samp[src];
+    }
+    if (tid == 0) {
+        sp.v = v;
+        sp.d = d;
+        sp.nb = 2 * v + 1;
+        uint32_t nbits = 1;
+        while ((1u << nbits) < 2 * v + 2) ++nbits;
+        sp.nbits = nbits;
+        sp.ndistinct = U;
+    }
+    __syncthreads();
+    for (uint32_t j = 1 + tid; j <= v; j += NT) {
+        const uint32_t delta = 31 - __clz(j);
+        const uint32_t p = j - (1u << delta);
+        const uint32_t r = ((2 * p + 1) << (d - 1 - delta)) - 1;
+        sp.tree[j] = sp.x[r];
+    }
+    for (uint32_t l = tid; l <= v; l += NT) {
+        uint32_t hl = 0;
+        if (l > 0 && l < v) {
+            const uint64_t z = sp.x[l - 1] ^ sp.x[l];
+            hl = z ? (uint32_t)(__clzll(z) >> 3) : 8u;
+        }
+        sp.hl[l] = (uint8_t)hl;
+        sp.zr[l] = (l < v && (sp.x[l] & 0xFF) == 0) ? 1 : 0;
+    }
+    __syncthreads();
+}
+
+}  // namespace ssd

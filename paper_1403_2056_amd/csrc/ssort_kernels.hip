@@ -1,0 +1,874 @@
+// HIP kernels of the string sample sorter for gfx950.
+//
+// Control flow of one sort (all enqueued on one stream, no host round trip):
+//   k_init            queue ring, control block, root task(s)
+//   [root step]       for large inputs the first classification step runs
+//                     across the whole GPU: k_root_sample (one workgroup),
+//                     k_root_classify (tiles), k_root_colscan (per bucket),
+//                     k_root_scatter (tiles), k_root_schedule (one workgroup)
+//   k_worker          persistent workgroups drain a device-side work queue of
+//                     segments; each segment step (sample, tree, classify,
+//                     count, prefix sum, stable redistribution) is done by one
+//                     workgroup, small children go to the LCP-aware base case
+//                     right away, large children are queued (one is kept)
+//   k_seam            LCPs at bucket boundaries from the separation depth
+//                     recorded when the boundary was created
+#include "ssort_kernels.h"
+
+namespace ssd {
+
+struct Task {
+    uint32_t begin, size, depth, meta, setbase;
+};
+
+__device__ __forceinline__ Rec load_rec(const Params &P, uint32_t meta, uint32_t pos) {
+    if (meta & M_IDENT_SRC) return make_rec(P.S, pos);
+    return (meta & M_PARITY) ? P.R1[pos] : P.R0[pos];
+}
+
+// A step writes its redistribution into the other record buffer.
+__device__ __forceinline__ bool out_is_r1(uint32_t meta) {
+    return (meta & M_IDENT_SRC) ? true : !(meta & M_PARITY);
+}
+
+__device__ __forceinline__ unsigned long long ld_rlx(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long add_agent(unsigned long long *p, unsigned long long v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Stable redistribution of one chunk (Algorithm 1, redistribution; parallel
+// form of the theorem's proof: per-workgroup counters and an interleaved
+// prefix sum).  The chunk holds up to NT*K elements laid out wave-contiguous:
+// element e = w*64*K + j*64 + lane.  Ranks inside a wave come from bucket
+// matching by ballots, waves are ordered through per-wave counters, and the
+// records are regrouped by bucket in LDS so that each bucket's run is written
+// contiguously.  run[b] is the output position of the chunk's first element
+// of bucket b and is advanced past the chunk.
+template <int K>
+struct ScatterLDS {
+    uint32_t wcnt[NW][NBPAD];
+    uint32_t tot[NBPAD];
+    uint32_t cs[NBPAD];
+    Rec rec[NT * K];
+    uint16_t b[NT * K];
+};
+
+template <int K>
+__device__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, const uint32_t (&m)[K],
+                              const Rec (&r)[K], uint32_t cnt, uint32_t *run, Rec *out, uint32_t nlim,
+                              unsigned long long *err) {
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint32_t nb = uni(sp.nb);
+    const int nbits = (int)uni(sp.nbits);
+    uint32_t *wc = &L.wcnt[0][0];
+    for (int i = tid; i < NW * NBPAD; i += NT) wc[i] = 0;
+    __syncthreads();
+    uint32_t rk[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t mj = m[j];
+        const uint64_t mask = match_any(mj, nbits);
+        // wave-synchronous: every lane reads the wave's count before the
+        // bucket's last lane advances it
+        const uint32_t base = L.wcnt[w][mj];
+        rk[j] = base + mbcnt(mask);
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 63 - (int)__clzll(mask)) L.wcnt[w][mj] = base + (uint32_t)__popcll(mask);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < nb; b += NT) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t t = L.wcnt[ww][b];
+            L.wcnt[ww][b] = c;
+            c += t;
+        }
+        L.tot[b] = c;
+        L.cs[b] = c;
+    }
+    __syncthreads();
+    block_scan(L.cs, (int)nb, tmp, true, AddOp(), 0u);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t e = (uint32_t)(w * 64 * K + j * 64 + lane);
+        if (e < cnt) {
+            const uint32_t mj = m[j];
+            const uint32_t slot = L.cs[mj] + L.wcnt[w][mj] + rk[j];
+            L.rec[slot] = r[j];
+            L.b[slot] = (uint16_t)mj;
+        }
+    }
+    __syncthreads();
+    for (uint32_t s = tid; s < cnt; s += NT) {
+        const uint32_t mb = L.b[s];
+        const uint32_t gp = run[mb] + (s - L.cs[mb]);
+        if (gp < nlim) out[gp] = L.rec[s];
+        else atomicOr(err, ERR_INTERNAL);
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < nb; b += NT) run[b] += L.tot[b];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// LCP-aware base case (semantics of LCP insertion sort, Algorithm 5: sorted
+// order, stable by input index, and the adjacent LCPs).  A chunk of up to C
+// strings from several groups; each group is sorted independently from its
+// common depth.  Rounds: gather the 8-byte key at the class depth, rank every
+// element inside its class by (key, index), then split classes at key
+// changes; adjacent elements whose keys differ get lcp = depth + equal leading
+// bytes, equal keys ending their strings are identical strings (lcp = length),
+// equal keys without an end go on at depth + 8.
+template <int C>
+struct BaseLDS {
+    uint64_t st[C];
+    uint64_t key[C];
+    uint32_t ln[C];
+    uint32_t id[C];
+    uint32_t d[C];
+    uint32_t scr[C];
+    uint16_t cst[C];
+    uint16_t ord[2][C];
+    uint8_t act[C];
+    uint32_t any;
+};
+
+// Group accessor: group g of the chunk has global start gstart(g), size
+// gsize(g), common depth gdepth(g) and chunk-local exclusive prefix gpre(g).
+template <int C, typename G>
+__device__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const Rec *src, uint32_t setbase,
+                           uint32_t ng, uint32_t M, const G &grp) {
+    const int tid = threadIdx.x;
+    auto find = [&](uint32_t q) -> uint32_t {
+        uint32_t lo = 0, hi = ng;           // largest g with gpre(g) <= q
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (grp.gpre(mid) <= q) lo = mid; else hi = mid;
+        }
+        return lo;
+    };
+    auto gpos = [&](uint32_t q) -> uint32_t {
+        const uint32_t g = find(q);
+        return grp.gstart(g) + (q - grp.gpre(g));
+    };
+    for (uint32_t q = tid; q < M; q += NT) {
+        const uint32_t g = find(q);
+        const Rec r = src[grp.gstart(g) + (q - grp.gpre(g))];
+        B.st[q] = r.st;
+        B.ln[q] = r.ln;
+        B.id[q] = r.id;
+        B.d[q] = grp.gdepth(g);
+        B.cst[q] = (uint16_t)grp.gpre(g);
+        B.ord[0][q] = (uint16_t)q;
+        B.act[q] = grp.gsize(g) >= 2 ? 1 : 0;
+    }
+    if (tid == 0) B.any = 0;
+    __syncthreads();
+    int cur = 0;
+    bool more = true;
+    while (more) {
+        for (uint32_t q = tid; q < M; q += NT)
+            if (B.act[q]) {
+                const uint32_t e = B.ord[cur][q];
+                B.key[e] = key_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], B.d[e]);
+            }
+        __syncthreads();
+        for (uint32_t q = tid; q < M; q += NT) {
+            const uint32_t e = B.ord[cur][q];
+            if (B.act[q]) {
+                const uint64_t k = B.key[e];
+                const uint32_t i = B.id[e];
+                const uint32_t c0 = B.cst[q];
+                uint32_t r = 0;
+                for (uint32_t j = c0; j < M && B.cst[j] == c0; ++j) {
+                    const uint32_t ee = B.ord[cur][j];
+                    const uint64_t kk = B.key[ee];
+                    r += (kk < k || (kk == k && B.id[ee] < i)) ? 1u : 0u;
+                }
+                B.ord[cur ^ 1][c0 + r] = (uint16_t)e;
+            } else {
+                B.ord[cur ^ 1][q] = (uint16_t)e;
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+        for (uint32_t q = tid; q < M; q += NT) {
+            const uint32_t e = B.ord[cur][q];
+            bool head = (q == B.cst[q]);
+            if (B.act[q] && !head) {
+                const uint32_t pe = B.ord[cur][q - 1];
+                const uint64_t k = B.key[e], pk = B.key[pe];
+                if (k != pk) {
+                    head = true;
+                    if (P.lcp) P.lcp[gpos(q)] = B.d[e] + (uint32_t)(__clzll(k ^ pk) >> 3);
+                } else if ((k & 0xFF) == 0) {
+                    if (P.lcp) P.lcp[gpos(q)] = B.ln[e];
+                }
+            }
+            B.scr[q] = head ? q : 0u;
+        }
+        __syncthreads();
+        block_scan(B.scr, (int)M, tmp, false, MaxOp(), 0u);
+        for (uint32_t q = tid; q < M; q += NT) {
+            const uint32_t nc = B.scr[q];
+            if (B.act[q]) {
+                const uint32_t e = B.ord[cur][q];
+                const bool two = (q > nc) || (q + 1 < M && B.scr[q + 1] == nc);
+                const bool go = two && ((B.key[e] & 0xFF) != 0);
+                B.act[q] = go ? 1 : 0;
+                if (go) {
+                    B.d[e] += 8;
+                    B.any = 1;
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t q = tid; q < M; q += NT) B.cst[q] = (uint16_t)B.scr[q];
+        more = uni(B.any) != 0;
+        __syncthreads();
+        if (tid == 0) B.any = 0;
+    }
+    for (uint32_t q = tid; q < M; q += NT) P.perm[gpos(q)] = B.id[B.ord[cur][q]] - setbase;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Per-workgroup state of the persistent worker.
+template <int K, int C>
+struct StepLDS {
+    Split sp;
+    uint32_t hist[NBPAD];     // strings per bucket
+    uint32_t bst[NBPAD];      // bucket start, relative to the segment
+    uint32_t run[NBPAD];      // next output position per bucket (absolute)
+    uint32_t cdep[NBPAD];     // common depth of each child bucket
+    uint32_t psz[NBPAD + 1];  // exclusive size prefix over the small buckets
+    uint16_t lsmall[NBPAD];
+    uint16_t llarge[NBPAD];
+    uint16_t lident[NBPAD];
+    uint16_t cfirst[NBPAD + 1];
+    uint32_t nsmall, nlarge, nident, nchunk;
+    unsigned long long best;
+    unsigned long long qpos;
+    uint32_t tmp[NW];
+    union {
+        struct {
+            uint64_t samp[SAMPLE_MAX + 1];
+            uint64_t srt[SAMPLE_MAX + 1];
+            uint32_t fl[SAMPLE_MAX + 1];
+        } s;
+        ScatterLDS<K> sc;
+        BaseLDS<C> base;
+    } u;
+};
+
+struct SmallGroups {   // groups = consecutive entries of the step's small-bucket list
+    const uint32_t *hist, *bst, *cdep, *psz;
+    const uint16_t *lsmall;
+    uint32_t k0, begin, pre0;
+    __device__ uint32_t gstart(uint32_t g) const { return begin + bst[lsmall[k0 + g]]; }
+    __device__ uint32_t gsize(uint32_t g) const { return hist[lsmall[k0 + g]]; }
+    __device__ uint32_t gdepth(uint32_t g) const { return cdep[lsmall[k0 + g]]; }
+    __device__ uint32_t gpre(uint32_t g) const { return psz[k0 + g] - pre0; }
+};
+
+struct OneGroup {
+    uint32_t start, size, depth;
+    __device__ uint32_t gstart(uint32_t) const { return start; }
+    __device__ uint32_t gsize(uint32_t) const { return size; }
+    __device__ uint32_t gdepth(uint32_t) const { return depth; }
+    __device__ uint32_t gpre(uint32_t) const { return 0; }
+};
+
+__device__ __forceinline__ unsigned long long uni64(unsigned long long x) {
+    return ((unsigned long long)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+
+// Wait until queue position `pos` holds a task.  Executed by every lane of a
+// wave with wave-uniform values only (no loop inside a divergent region: a
+// spin loop run by one lane next to barriers can be lowered so that the other
+// lanes pass a barrier without it).  Polls with relaxed agent-scope loads (no
+// cache invalidation per poll), sleeps between polls, and issues one acquire
+// fence when the task is there.  Returns 1 (task ready), 0 (queue drained:
+// nothing pending, so nothing can be enqueued any more) or -1 (device error or
+// the wait limit, by wall clock or by poll count).
+__device__ int poll_slot(const Params &P, Slot *s, unsigned long long pos) {
+    const unsigned long long t0 = wall_clock64();
+    for (unsigned long long it = 0;; ++it) {
+        if (uni64(ld_rlx(&s->seq)) == pos + 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return 1;
+        }
+        if (uni64(ld_rlx(&P.ctl->pending)) == 0) return 0;
+        if (uni64(ld_rlx(&P.ctl->error)) != 0) return -1;
+        if (wall_clock64() - t0 > P.limit_ticks || it > P.limit_iters) {
+            if (lane_id() == 0)
+                __hip_atomic_fetch_or(&P.ctl->error, ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+        __builtin_amdgcn_s_sleep(10);
+    }
+}
+
+// Publish one task (already counted in `pending`) at queue position pos.  One
+// attempt, no waiting: the ring is sized so that the slot's previous occupant
+// (pos - capacity) has long been consumed; if it has not, the sort fails with
+// a device error instead of overwriting it.
+__device__ void publish(const Params &P, unsigned long long pos, const Task &t) {
+    Slot *s = &P.ring[pos & P.ring_mask];
+    if (ld_rlx(&s->seq) != pos) {
+        __hip_atomic_fetch_or(&P.ctl->error, ERR_QUEUE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    s->begin = t.begin;
+    s->size = t.size;
+    s->depth = t.depth;
+    s->meta = t.meta;
+    s->setbase = t.setbase;
+    st_rel(&s->seq, pos + 1);
+}
+
+// Identical strings (an equality bucket whose splitter ends the string):
+// already in input-index order; lcp between them is their length.
+__device__ void finish_ident(const Params &P, const Rec *src, uint32_t start, uint32_t cnt, uint32_t setbase) {
+    for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+        const Rec r = src[start + i];
+        P.perm[start + i] = r.id - setbase;
+        if (P.lcp && i > 0) P.lcp[start + i] = r.ln;
+    }
+}
+
+// One classification step of a segment by one workgroup.  Returns true when
+// `t` has been replaced by a child segment this workgroup continues with.
+template <int K, int C>
+__device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint32_t begin = t.begin, S = t.size, h = t.depth, meta = t.meta;
+    auto kload = [&](uint32_t e, uint32_t hh) -> uint64_t {
+        const Rec r = load_rec(P, meta, begin + e);
+        return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
+    };
+    select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, L.u.s.samp,
+                     L.u.s.srt, L.u.s.fl, L.tmp, kload);
+    for (int b = tid; b < NBPAD; b += NT) L.hist[b] = 0;
+    if (tid == 0) {
+        __hip_atomic_fetch_add(&P.ctl->st_segments, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&P.ctl->st_strings, (unsigned long long)S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(&P.ctl->st_maxdepth, (unsigned long long)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t nb = uni(L.sp.nb);
+    const int nbits = (int)uni(L.sp.nbits);
+    const uint32_t CK = NT * K;
+    // classify and count
+    for (uint32_t c0 = 0; c0 < S; c0 += CK) {
+        Rec r[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+            if (e < S) r[j] = load_rec(P, meta, begin + e);
+        }
+        uint64_t k[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+            k[j] = (e < S) ? key_at(P.S.chars, P.S.nchars, r[j].st, r[j].ln, h) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+            const bool valid = e < S;
+            const uint32_t m = valid ? classify(k[j], L.sp) : nb;
+            const uint64_t mask = match_any(m, nbits);
+            if (valid && lane == 63 - (int)__clzll(mask)) atomicAdd(&L.hist[m], (uint32_t)__popcll(mask));
+            if (valid) P.bkt[begin + e] = (uint16_t)m;
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < NBPAD; b += NT) L.bst[b] = (uint32_t)b < nb ? L.hist[b] : 0u;
+    __syncthreads();
+    block_scan(L.bst, (int)nb, L.tmp, true, AddOp(), 0u);
+    for (int b = tid; b < NBPAD; b += NT) L.run[b] = begin + L.bst[b];
+    __syncthreads();
+    const bool to1 = out_is_r1(meta);
+    Rec *out = to1 ? P.R1 : P.R0;
+    for (uint32_t c0 = 0; c0 < S; c0 += CK) {
+        Rec r[K];
+        uint32_t m[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+            if (e < S) {
+                r[j] = load_rec(P, meta, begin + e);
+                m[j] = P.bkt[begin + e];
+            } else {
+                m[j] = nb;
+            }
+        }
+        scatter_chunk<K>(L.u.sc, L.tmp, L.sp, m, r, min(CK, S - c0), L.run, out, P.S.n, &P.ctl->error);
+    }
+    // the redistributed records must be visible to every wave and every workgroup
+    __threadfence();
+    __syncthreads();
+
+    // ---- children (Algorithm 1 output: bucket i has common prefix h + h'_{i/2}
+    // for even i, except the outer buckets which keep h, and h + 8 for odd i) ----
+    const uint32_t cpar = to1 ? M_PARITY : 0u;
+    if (tid == 0) {
+        L.nlarge = 0;
+        L.nident = 0;
+        L.best = 0;
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < nb; b += NT) {
+        const uint32_t cnt = L.hist[b], st = L.bst[b];
+        uint32_t small = 0;
+        if (cnt) {
+            const uint32_t l = b >> 1;
+            const bool odd = b & 1;
+            L.cdep[b] = odd ? h + 8 : ((b == 0 || b == nb - 1) ? h : h + L.sp.hl[l]);
+            if (P.lcp && st > 0) P.lcp[begin + st] = SEAM | h;
+            if (odd && L.sp.zr[l]) {
+                L.lident[atomicAdd(&L.nident, 1u)] = (uint16_t)b;
+            } else if (cnt <= P.tbase) {
+                small = 1;
+            } else {
+                const uint32_t k = atomicAdd(&L.nlarge, 1u);
+                L.llarge[k] = (uint16_t)b;
+                atomicMax(&L.best, ((unsigned long long)cnt << 16) | k);
+            }
+        }
+        L.psz[b] = small;
+    }
+    __syncthreads();
+    const uint32_t nsmall = uni(block_scan(L.psz, (int)nb, L.tmp, true, AddOp(), 0u));
+    for (uint32_t b = tid; b < nb; b += NT) {
+        const uint32_t cnt = L.hist[b];
+        if (cnt && cnt <= P.tbase && !((b & 1) && L.sp.zr[b >> 1])) L.lsmall[L.psz[b]] = (uint16_t)b;
+    }
+    __syncthreads();
+    // size prefix over the small list
+    for (uint32_t k = tid; k < nsmall; k += NT) L.psz[k] = L.hist[L.lsmall[k]];
+    __syncthreads();
+    const uint32_t small_total = block_scan(L.psz, (int)nsmall, L.tmp, true, AddOp(), 0u);
+    if (tid == 0) L.psz[nsmall] = small_total;
+    // large children: keep the largest, queue the others
+    const uint32_t nlarge = uni(L.nlarge);
+    const uint32_t keep = uni((uint32_t)(L.best & 0xFFFF));
+    if (tid == 0 && nlarge > 1) {
+        add_agent(&P.ctl->pending, (unsigned long long)(nlarge - 1));
+        L.qpos = add_agent(&P.ctl->tail, (unsigned long long)(nlarge - 1));
+    }
+    __syncthreads();
+    if (nlarge > 1) {
+        for (uint32_t k = tid; k < nlarge; k += NT) {
+            if (k == keep) continue;
+            const uint32_t b = L.llarge[k];
+            Task c{begin + L.bst[b], L.hist[b], L.cdep[b], cpar, t.setbase};
+            publish(P, L.qpos + (k < keep ? k : k - 1), c);
+        }
+    }
+    __syncthreads();
+    // identical buckets
+    const uint32_t nident = uni(L.nident);
+    for (uint32_t k = 0; k < nident; ++k) {
+        const uint32_t b = L.lident[k];
+        finish_ident(P, out, begin + L.bst[b], L.hist[b], t.setbase);
+    }
+    // small buckets: base-case chunks of at most C strings, never splitting a group
+    if (nsmall) {
+        const uint32_t cap = (P.tbase * 2 <= (uint32_t)C) ? (uint32_t)C - P.tbase : 0u;
+        for (uint32_t k = tid; k < nsmall; k += NT) {
+            const uint32_t ck = cap ? L.psz[k] / cap : k;
+            const uint32_t cp = k ? (cap ? L.psz[k - 1] / cap : k - 1) : 0xFFFFFFFFu;
+            if (ck != cp) L.cfirst[ck] = (uint16_t)k;
+            if (k == nsmall - 1) L.nchunk = ck + 1;
+        }
+        __syncthreads();
+        const uint32_t nchunk = uni(L.nchunk);
+        if (tid == 0) L.cfirst[nchunk] = (uint16_t)nsmall;
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_fetch_add(&P.ctl->st_base, (unsigned long long)nsmall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (uint32_t c = 0; c < nchunk; ++c) {
+            const uint32_t k0 = uni(L.cfirst[c]), k1 = uni(L.cfirst[c + 1]);
+            SmallGroups g{L.hist, L.bst, L.cdep, L.psz, L.lsmall, k0, begin, L.psz[k0]};
+            base_chunk<C>(P, L.u.base, L.tmp, out, t.setbase, k1 - k0, uni(L.psz[k1] - L.psz[k0]), g);
+        }
+    }
+    __syncthreads();
+    if (nlarge >= 1) {
+        const uint32_t b = uni(L.llarge[keep]);
+        t = Task{begin + uni(L.bst[b]), uni(L.hist[b]), uni(L.cdep[b]), cpar, t.setbase};
+        __syncthreads();
+        return true;
+    }
+    return false;
+}
+
+template <int K, int C>
+__device__ void run_task(const Params &P, Task t, StepLDS<K, C> &L) {
+    if (t.size == 0) return;
+    if (t.meta & M_IDENT) {
+        const Rec *src = (t.meta & M_PARITY) ? P.R1 : P.R0;
+        finish_ident(P, src, t.begin, t.size, t.setbase);
+        return;
+    }
+    if (t.size <= P.tbase) {
+        if (t.meta & M_IDENT_SRC) {
+            // a whole set small enough for the base case: stage its records first
+            for (uint32_t i = threadIdx.x; i < t.size; i += NT) P.R0[t.begin + i] = make_rec(P.S, t.begin + i);
+            __threadfence();
+            __syncthreads();
+            t.meta = 0;
+        }
+        const Rec *src = (t.meta & M_PARITY) ? P.R1 : P.R0;
+        OneGroup g{t.begin, t.size, t.depth};
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&P.ctl->st_base, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, 1, t.size, g);
+        return;
+    }
+    while (seg_step<K, C>(P, t, L)) {
+    }
+}
+
+template <int K, int C>
+__global__ __launch_bounds__(NT) void k_worker(Params P) {
+    __shared__ StepLDS<K, C> L;
+    __shared__ unsigned long long claim;
+    __shared__ int outcome[NW];
+    if (P.ctl->error) return;
+    const int w = threadIdx.x >> 6;
+    for (;;) {
+        // a barrier between the previous task's thread-0 epilogue and this
+        // claim keeps the two thread-0 regions from being merged across the
+        // loop's back edge (which would let the other lanes loop without it)
+        __syncthreads();
+        if (threadIdx.x == 0)
+            claim = __hip_atomic_fetch_add(&P.ctl->head, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const unsigned long long pos = uni64(claim);
+        Slot *s = &P.ring[pos & P.ring_mask];
+        const int oc = poll_slot(P, s, pos);
+        if (lane_id() == 0) outcome[w] = oc;
+        __syncthreads();
+        // waves agree unless one hit an error or the wait limit: then all stop
+        int o = 1;
+        for (int ww = 0; ww < NW; ++ww) o = min(o, outcome[ww]);
+        o = (int)uni((uint32_t)o);
+        if (o <= 0) break;
+        const Task t{uni(s->begin), uni(s->size), uni(s->depth), uni(s->meta), uni(s->setbase)};
+        __syncthreads();   // every wave has read the slot: hand it back to the ring
+        if (threadIdx.x == 0) st_rel(&s->seq, pos + P.ring_mask + 1);
+        if (t.begin > P.S.n || t.size > P.S.n - t.begin) {
+            if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        } else {
+            run_task<K, C>(P, t, L);
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&P.ctl->pending, ~0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: queue ring sequence numbers, control block, root tasks.
+// mode 0: no root task (the whole-GPU root step follows), 1: one root task for
+// [0, n), 2: one root task per set of a batch.
+__global__ void k_init(Params P, uint32_t mode, unsigned long long cap) {
+    const unsigned long long i0 = blockIdx.x * (unsigned long long)NT + threadIdx.x;
+    const unsigned long long stride = (unsigned long long)gridDim.x * NT;
+    const uint32_t nroot = mode == 0 ? 0u : (mode == 1 ? 1u : P.m);
+    for (unsigned long long i = i0; i < cap; i += stride) {
+        Slot *s = &P.ring[i];
+        if (i < nroot) {
+            uint32_t b, e;
+            if (mode == 1) { b = 0; e = P.S.n; }
+            else { b = P.set_begin[i]; e = P.set_begin[i + 1]; }
+            s->begin = b;
+            s->size = e - b;
+            s->depth = 0;
+            s->meta = M_IDENT_SRC;
+            s->setbase = mode == 2 ? b : 0u;
+            s->seq = i + 1;
+            if (P.lcp && e > b) P.lcp[b] = 0;
+        } else {
+            s->seq = i;
+        }
+    }
+    if (i0 == 0) {
+        Ctl *c = P.ctl;
+        c->head = 0;
+        c->tail = nroot;
+        c->pending = nroot;
+        c->error = 0;
+        c->st_segments = c->st_strings = c->st_base = c->st_maxdepth = 0;
+        if (P.lcp && P.S.n) P.lcp[0] = 0;
+    }
+}
+
+// Optional input validation: bounds and zero bytes.
+__global__ void k_validate(Params P) {
+    const uint32_t i0 = blockIdx.x * NT + threadIdx.x, stride = gridDim.x * NT;
+    if (P.S.flags & TO_END) {
+        for (uint64_t p = i0; p < P.S.nchars; p += stride)
+            if (P.S.chars[p] == 0) atomicOr(&P.ctl->error, ERR_ZERO);
+        for (uint32_t i = i0; i < P.S.n; i += stride)
+            if (P.S.off[i] > P.S.nchars || P.S.nchars - P.S.off[i] >= 0x80000000ull) atomicOr(&P.ctl->error, ERR_BOUNDS);
+        return;
+    }
+    for (uint32_t i = i0; i < P.S.n; i += stride) {
+        const uint64_t st = P.S.off[i];
+        uint64_t ln;
+        if (P.S.len) ln = P.S.len[i];
+        else ln = P.S.off[i + 1] >= st ? P.S.off[i + 1] - st : ~0ull;
+        if (st > P.S.nchars || ln > P.S.nchars - st || ln >= 0x80000000ull) {
+            atomicOr(&P.ctl->error, ERR_BOUNDS);
+            continue;
+        }
+        for (uint64_t p = 0; p < ln; ++p)
+            if (P.S.chars[st + p] == 0) { atomicOr(&P.ctl->error, ERR_ZERO); break; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Root step across the whole GPU (the fully parallel step of pS5).
+struct RootSampleLDS {
+    Split sp;
+    uint64_t samp[SAMPLE_MAX + 1];
+    uint64_t srt[SAMPLE_MAX + 1];
+    uint32_t fl[SAMPLE_MAX + 1];
+    uint32_t tmp[NW];
+};
+
+__global__ __launch_bounds__(NT) void k_root_sample(Params P, uint32_t depth) {
+    __shared__ RootSampleLDS L;
+    if (P.ctl->error) return;
+    auto kload = [&](uint32_t e, uint32_t hh) -> uint64_t {
+        const Rec r = make_rec(P.S, e);
+        return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
+    };
+    select_splitters(L.sp, P.S.n, depth, 0x2545F491u ^ P.S.n, P.vmax, L.samp, L.srt, L.fl, L.tmp, kload);
+    const uint32_t *src = (const uint32_t *)&L.sp;
+    uint32_t *dst = (uint32_t *)P.gsplit;
+    for (uint32_t i = threadIdx.x; i < sizeof(Split) / 4; i += NT) dst[i] = src[i];
+}
+
+__device__ void load_split(Split &sp, const Split *g) {
+    const uint32_t *src = (const uint32_t *)g;
+    uint32_t *dst = (uint32_t *)&sp;
+    for (uint32_t i = threadIdx.x; i < sizeof(Split) / 4; i += NT) dst[i] = src[i];
+    __syncthreads();
+}
+
+template <int K>
+__global__ __launch_bounds__(NT) void k_root_classify(Params P, uint32_t depth) {
+    __shared__ Split sp;
+    __shared__ uint32_t hist[NBPAD];
+    if (P.ctl->error) return;
+    load_split(sp, P.gsplit);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int b = tid; b < NBPAD; b += NT) hist[b] = 0;
+    __syncthreads();
+    const uint32_t n = P.S.n, nb = uni(sp.nb);
+    const int nbits = (int)uni(sp.nbits);
+    const uint32_t c0 = blockIdx.x * (uint32_t)(NT * K);
+    Rec r[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+        if (e < n) r[j] = make_rec(P.S, e);
+    }
+    uint64_t k[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+        k[j] = e < n ? key_at(P.S.chars, P.S.nchars, r[j].st, r[j].ln, depth) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+        const bool valid = e < n;
+        const uint32_t m = valid ? classify(k[j], sp) : nb;
+        const uint64_t mask = match_any(m, nbits);
+        if (valid && lane == 63 - (int)__clzll(mask)) atomicAdd(&hist[m], (uint32_t)__popcll(mask));
+        if (valid) P.bkt[e] = (uint16_t)m;
+    }
+    __syncthreads();
+    for (uint32_t b = tid; b < nb; b += NT) P.hist[(size_t)b * P.ntiles + blockIdx.x] = hist[b];
+}
+
+// Exclusive scan over the tiles of one bucket (bucket-major layout), giving
+// every (tile, bucket) pair its offset inside the bucket; totals per bucket.
+__global__ __launch_bounds__(NT) void k_root_colscan(Params P) {
+    __shared__ uint32_t tmp[NW];
+    __shared__ uint32_t part[NT];
+    if (P.ctl->error) return;
+    const uint32_t b = blockIdx.x;
+    if (b >= P.gsplit->nb) return;
+    uint32_t *row = P.hist + (size_t)b * P.ntiles;
+    const uint32_t T = P.ntiles;
+    const uint32_t per = (T + NT - 1) / NT;
+    const uint32_t lo = threadIdx.x * per, hi = min(T, lo + per);
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < hi; ++i) s += row[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    const uint32_t total = block_scan(part, NT, tmp, true, AddOp(), 0u);
+    uint32_t run = part[threadIdx.x];
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t x = row[i];
+        row[i] = run;
+        run += x;
+    }
+    if (threadIdx.x == 0) P.totals[b] = total;
+}
+
+template <int K>
+struct RootScatterLDS {
+    Split sp;
+    uint32_t run[NBPAD];
+    uint32_t tmp[NW];
+    ScatterLDS<K> sc;
+};
+
+template <int K>
+__global__ __launch_bounds__(NT) void k_root_scatter(Params P) {
+    __shared__ RootScatterLDS<K> L;
+    if (P.ctl->error) return;
+    load_split(L.sp, P.gsplit);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint32_t nb = uni(L.sp.nb), n = P.S.n;
+    for (uint32_t b = tid; b < NBPAD; b += NT) L.run[b] = b < nb ? P.totals[b] : 0u;
+    __syncthreads();
+    block_scan(L.run, (int)nb, L.tmp, true, AddOp(), 0u);
+    for (uint32_t b = tid; b < nb; b += NT) L.run[b] += P.hist[(size_t)b * P.ntiles + blockIdx.x];
+    __syncthreads();
+    const uint32_t c0 = blockIdx.x * (uint32_t)(NT * K);
+    Rec r[K];
+    uint32_t m[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+        if (e < n) {
+            r[j] = make_rec(P.S, e);
+            m[j] = P.bkt[e];
+        } else {
+            m[j] = nb;
+        }
+    }
+    scatter_chunk<K>(L.sc, L.tmp, L.sp, m, r, min((uint32_t)(NT * K), n - c0), L.run, P.R1, n, &P.ctl->error);
+}
+
+// Children of the root step become the first tasks of the queue.
+__global__ __launch_bounds__(NT) void k_root_schedule(Params P, uint32_t depth) {
+    __shared__ Split sp;
+    __shared__ uint32_t bst[NBPAD];
+    __shared__ uint32_t fl[NBPAD];
+    __shared__ uint32_t tmp[NW];
+    if (P.ctl->error) return;
+    load_split(sp, P.gsplit);
+    const uint32_t nb = uni(sp.nb);
+    for (uint32_t b = threadIdx.x; b < NBPAD; b += NT) {
+        bst[b] = b < nb ? P.totals[b] : 0u;
+        fl[b] = (b < nb && P.totals[b]) ? 1u : 0u;
+    }
+    __syncthreads();
+    block_scan(bst, (int)nb, tmp, true, AddOp(), 0u);
+    const uint32_t k = block_scan(fl, (int)nb, tmp, true, AddOp(), 0u);
+    for (uint32_t b = threadIdx.x; b < nb; b += NT) {
+        const uint32_t cnt = P.totals[b];
+        if (!cnt) continue;
+        const uint32_t st = bst[b], l = b >> 1;
+        const bool odd = b & 1;
+        const uint32_t cd = odd ? depth + 8 : ((b == 0 || b == nb - 1) ? depth : depth + sp.hl[l]);
+        if (P.lcp && st > 0) P.lcp[st] = SEAM | depth;
+        Slot *s = &P.ring[fl[b]];
+        s->begin = st;
+        s->size = cnt;
+        s->depth = cd;
+        s->meta = M_PARITY | ((odd && sp.zr[l]) ? M_IDENT : 0u);
+        s->setbase = 0;
+        s->seq = (unsigned long long)fl[b] + 1;
+    }
+    if (threadIdx.x == 0) {
+        P.ctl->tail = k;
+        P.ctl->pending = k;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Boundary LCPs: a position still holding SEAM|h was the first string of a
+// bucket created by a step at depth h; its predecessor lies in an earlier
+// bucket of that step, so their keys at depth h differ and the LCP is h plus
+// the equal leading bytes of the two keys.
+__global__ void k_seam(Params P) {
+    const uint32_t n = P.S.n;
+    for (uint32_t p = blockIdx.x * NT + threadIdx.x + 1; p < n; p += gridDim.x * NT) {
+        const uint32_t v = P.lcp[p];
+        if (!(v & SEAM)) continue;
+        const uint32_t h = v & ~SEAM;
+        uint32_t base = 0;
+        if (P.set_begin) {
+            uint32_t lo = 0, hi = P.m;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (P.set_begin[mid] <= p) lo = mid; else hi = mid;
+            }
+            base = P.set_begin[lo];
+        }
+        const Rec a = make_rec(P.S, P.perm[p - 1] + base);
+        const Rec b = make_rec(P.S, P.perm[p] + base);
+        const uint64_t ka = key_at(P.S.chars, P.S.nchars, a.st, a.ln, h);
+        const uint64_t kb = key_at(P.S.chars, P.S.nchars, b.st, b.ln, h);
+        const uint64_t z = ka ^ kb;
+        P.lcp[p] = h + (z ? (uint32_t)(__clzll(z) >> 3) : 8u);
+    }
+}
+
+// Debug dump of one root step.
+__global__ void k_debug_dump(Params P, uint32_t depth, uint64_t *keys, uint64_t *split, uint64_t *tree,
+                             uint32_t *info, uint16_t *bucket, uint32_t *hist, uint32_t *perm) {
+    const Split *sp = P.gsplit;
+    const uint32_t n = P.S.n;
+    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const Rec r = make_rec(P.S, i);
+        keys[i] = key_at(P.S.chars, P.S.nchars, r.st, r.ln, depth);
+        bucket[i] = P.bkt[i];
+        perm[i] = P.R1[i].id;
+    }
+    if (blockIdx.x == 0) {
+        for (uint32_t j = threadIdx.x; j < 256; j += NT) {
+            split[j] = j < sp->v ? sp->x[j] : 0;
+            tree[j] = (j < sp->v) ? sp->tree[j + 1] : 0;
+        }
+        for (uint32_t b = threadIdx.x; b < NBPAD; b += NT) hist[b] = b < sp->nb ? P.totals[b] : 0;
+        if (threadIdx.x == 0) {
+            info[0] = sp->v;
+            info[1] = sp->d;
+            info[2] = sp->ndistinct;
+            info[3] = 0;
+        }
+    }
+}
+
+// explicit instantiations used by the host code
+template __global__ void k_worker<4, 512>(Params);
+template __global__ void k_worker<4, 1024>(Params);
+template __global__ void k_worker<8, 512>(Params);
+template __global__ void k_worker<8, 1024>(Params);
+template __global__ void k_root_classify<4>(Params, uint32_t);
+template __global__ void k_root_classify<8>(Params, uint32_t);
+template __global__ void k_root_scatter<4>(Params);
+template __global__ void k_root_scatter<8>(Params);
+
+}  // namespace ssd

@@ -1,0 +1,242 @@
+"""Thin ctypes binding of libssort.so (argument marshalling only).
+
+Every step of the sort runs in the HIP kernels of libssort.so; PyTorch only
+provides device memory and the current stream.  There is no fallback: if the
+library or a GPU is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssort.so")
+
+SSORT_TO_END = 1
+SSORT_VALIDATE = 1
+
+STATUS = {
+    0: "SSORT_OK", 1: "SSORT_EINVAL", 2: "SSORT_ENOMEM", 3: "SSORT_EWORKSPACE", 4: "SSORT_EBOUNDS",
+    5: "SSORT_EZEROBYTE", 6: "SSORT_EDEVICE", 7: "SSORT_EBUSY", 8: "SSORT_ETIMEOUT", 9: "SSORT_ENOTFOUND",
+}
+
+
+class SsortError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+
+
+class Strings(ctypes.Structure):
+    _fields_ = [("chars", ctypes.c_void_p), ("nchars", ctypes.c_uint64), ("offsets", ctypes.c_void_p),
+                ("lengths", ctypes.c_void_p), ("n", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("v", ctypes.c_uint32), ("keys_per_thread", ctypes.c_uint32),
+                ("base_threshold", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {"v": self.v, "keys_per_thread": self.keys_per_thread,
+                "base_threshold": self.base_threshold, "flags": self.flags}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("segments", ctypes.c_uint64), ("strings", ctypes.c_uint64),
+                ("base_groups", ctypes.c_uint64), ("max_depth", ctypes.c_uint64)]
+
+
+_lib = None
+
+# every entry point declared in include/ssort.h, with its ctypes signature
+_SIGS = {
+    "ssort_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ssort_destroy": (None, [ctypes.c_void_p]),
+    "ssort_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Tuning)]),
+    "ssort_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "ssort_sort": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "ssort_sort_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_void_p,
+                                          ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p]),
+    "ssort_query_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ssort_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_void_p]),
+    "ssort_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "ssort_device_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "ssort_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ssort_debug_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_uint32,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Load libssort.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SsortError(rc, what)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def strings_to_device(ss, device="cuda"):
+    """Copy a host string set (workloads.StringSet-like) to device tensors."""
+    import torch
+    chars = torch.from_numpy(np.ascontiguousarray(ss.chars) if len(ss.chars) else np.zeros(1, np.uint8))
+    off = torch.from_numpy(np.ascontiguousarray(ss.offsets).view(np.int64) if len(ss.offsets)
+                           else np.zeros(1, np.int64))
+    ln = None
+    if ss.lengths is not None:
+        ln = torch.from_numpy(np.ascontiguousarray(ss.lengths).view(np.int32)).to(device)
+    return DeviceStrings(chars.to(device), len(ss.chars), off.to(device), ln, ss.n, ss.flags)
+
+
+class DeviceStrings:
+    """Device-resident string set: chars (uint8), offsets (int64 viewed as
+    uint64), optional lengths (int32 viewed as uint32), n, flags."""
+
+    def __init__(self, chars, nchars, offsets, lengths, n, flags):
+        self.chars, self.nchars, self.offsets, self.lengths = chars, int(nchars), offsets, lengths
+        self.n, self.flags = int(n), int(flags)
+
+    def struct(self) -> Strings:
+        return Strings(_ptr(self.chars), self.nchars, _ptr(self.offsets), _ptr(self.lengths), self.n, self.flags)
+
+
+class Sorter:
+    """One library context on one GPU plus a workspace it grows on demand."""
+
+    def __init__(self, device: int = 0, v: int = 255, keys_per_thread: int = 4, base_threshold: int = 128,
+                 flags: int = 0):
+        import torch
+        self.device = device
+        self.tuning = Tuning(v, keys_per_thread, base_threshold, flags)
+        h = ctypes.c_void_p()
+        _check(lib().ssort_create(device, ctypes.byref(self.tuning), ctypes.byref(h)), "ssort_create")
+        self._h = h
+        self._ws = None
+        self._torch = torch
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ssort_destroy(self._h)
+            self._h = None
+
+    def set_wait_limit(self, ms: int):
+        _check(lib().ssort_set_wait_limit(self._h, ms), "ssort_set_wait_limit")
+
+    def device_info(self) -> dict:
+        a = (ctypes.c_uint64 * 4)()
+        _check(lib().ssort_device_info(self._h, a), "ssort_device_info")
+        return {"cus": a[0], "worker_blocks": a[1], "wall_khz": a[2], "device": a[3]}
+
+    def workspace_bytes(self, n: int, m: int = 1) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().ssort_workspace_bytes(self._h, n, m, ctypes.byref(b)), "ssort_workspace_bytes")
+        return b.value
+
+    def workspace(self, n: int, m: int = 1):
+        need = self.workspace_bytes(n, m)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = self._torch.empty(need, dtype=self._torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def sort(self, s: DeviceStrings, with_lcp: bool = True, out_perm=None, out_lcp=None, ws=None, stream=None):
+        """Enqueue a sort; returns (perm, lcp) int32 tensors holding uint32 values."""
+        torch = self._torch
+        dev = f"cuda:{self.device}"
+        n = s.n
+        if out_perm is None:
+            out_perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if with_lcp and out_lcp is None:
+            out_lcp = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if ws is None:
+            ws = self.workspace(n)
+        st = s.struct()
+        _check(lib().ssort_sort(self._h, ctypes.byref(st), _ptr(out_perm), _ptr(out_lcp) if with_lcp else None,
+                                _ptr(ws), ws.numel(), _stream(stream)), "ssort_sort")
+        return out_perm[:n], (out_lcp[:n] if with_lcp else None)
+
+    def sort_batched(self, s: DeviceStrings, set_begin, with_lcp: bool = True, out_perm=None, out_lcp=None,
+                     ws=None, stream=None):
+        torch = self._torch
+        dev = f"cuda:{self.device}"
+        n = s.n
+        m = set_begin.numel() - 1
+        if out_perm is None:
+            out_perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if with_lcp and out_lcp is None:
+            out_lcp = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if ws is None:
+            ws = self.workspace(n, m)
+        st = s.struct()
+        _check(lib().ssort_sort_batched(self._h, ctypes.byref(st), _ptr(set_begin), m, _ptr(out_perm),
+                                        _ptr(out_lcp) if with_lcp else None, _ptr(ws), ws.numel(),
+                                        _stream(stream)), "ssort_sort_batched")
+        return out_perm[:n], (out_lcp[:n] if with_lcp else None)
+
+    def query_error(self, stream=None) -> int:
+        return lib().ssort_query_error(self._h, _stream(stream))
+
+    def stats(self, stream=None) -> dict:
+        st = Stats()
+        _check(lib().ssort_stats(self._h, ctypes.byref(st), _stream(stream)), "ssort_stats")
+        return {"segments": st.segments, "strings": st.strings, "base_groups": st.base_groups,
+                "max_depth": st.max_depth}
+
+    def debug_step(self, s: DeviceStrings, depth: int = 0, stream=None) -> dict:
+        torch = self._torch
+        dev = f"cuda:{self.device}"
+        n = s.n
+        keys = torch.empty(n, dtype=torch.int64, device=dev)
+        split = torch.empty(256, dtype=torch.int64, device=dev)
+        tree = torch.empty(256, dtype=torch.int64, device=dev)
+        info = torch.empty(4, dtype=torch.int32, device=dev)
+        bucket = torch.empty(n, dtype=torch.int16, device=dev)
+        hist = torch.empty(512, dtype=torch.int32, device=dev)
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+        ws = self.workspace(n)
+        st = s.struct()
+        _check(lib().ssort_debug_step(self._h, ctypes.byref(st), depth, _ptr(keys), _ptr(split), _ptr(tree),
+                                      _ptr(info), _ptr(bucket), _ptr(hist), _ptr(perm), _ptr(ws), ws.numel(),
+                                      _stream(stream)), "ssort_debug_step")
+        torch.cuda.synchronize()
+        out = {"keys": keys.cpu().numpy().view(np.uint64), "split": split.cpu().numpy().view(np.uint64),
+               "tree": tree.cpu().numpy().view(np.uint64), "info": info.cpu().numpy().view(np.uint32),
+               "bucket": bucket.cpu().numpy().view(np.uint16), "hist": hist.cpu().numpy().view(np.uint32),
+               "perm": perm.cpu().numpy().view(np.uint32)}
+        v = int(out["info"][0])
+        out["split"] = out["split"][:v]
+        out["tree"] = out["tree"][:v]
+        out["hist"] = out["hist"][:2 * v + 1]
+        return out
+
+
+def to_numpy_u32(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)

@@ -1,0 +1,184 @@
+"""Parity of the HIP path with the CPU oracle, element by element (bit-exact
+permutation and LCP array), through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_2056_amd import workloads as W
+from tests.cases import adversarial
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sorter():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_2056_amd import ssort
+    s = ssort.Sorter(0)
+    s.set_wait_limit(10000)
+    return s
+
+
+def gpu_sort(sorter, ss, with_lcp=True):
+    from paper_1403_2056_amd import ssort
+    d = ssort.strings_to_device(ss)
+    perm, lcp = sorter.sort(d, with_lcp=with_lcp)
+    torch.cuda.synchronize()
+    err = sorter.query_error()
+    assert err == 0, f"device error {err}"
+    p = ssort.to_numpy_u32(perm).copy()
+    h = ssort.to_numpy_u32(lcp).copy() if with_lcp else None
+    return p, h
+
+
+def assert_parity(sorter, ss, label=""):
+    print(f"[parity] {label} n={ss.n}", flush=True)
+    p, h = gpu_sort(sorter, ss)
+    rp, rh = oracle.sort(ss)
+    if not np.array_equal(p, rp):
+        bad = int(np.nonzero(p != rp)[0][0])
+        raise AssertionError(f"{label}: perm differs first at {bad}: gpu {p[bad-2:bad+3]} oracle {rp[bad-2:bad+3]}")
+    if not np.array_equal(h, rh):
+        bad = int(np.nonzero(h != rh)[0][0])
+        raise AssertionError(f"{label}: lcp differs first at {bad}: gpu {h[bad-2:bad+3]} oracle {rh[bad-2:bad+3]}")
+
+
+def test_device_info(sorter):
+    info = sorter.device_info()
+    print("[device]", info, flush=True)
+    assert info["cus"] == 256
+    assert 10_000 <= info["wall_khz"] <= 1_000_000
+
+
+def test_debug_step_rows(sorter):
+    """One classification step: keys (8-byte big-endian gather), splitters and
+    level-order tree, bucket numbers, counts and the stable redistribution."""
+    from paper_1403_2056_amd import ssort
+    ss = W.plain(100000, seed=14)
+    for depth in (0, 3):
+        out = sorter.debug_step(ssort.strings_to_device(ss), depth)
+        keys = oracle.keys(ss, np.arange(ss.n), depth)
+        assert np.array_equal(out["keys"], keys)
+        x = out["split"]
+        v = len(x)
+        assert v == 2 ** int(out["info"][1]) - 1
+        assert np.all(x[1:] >= x[:-1])
+        assert set(x.tolist()) <= set(keys.tolist())
+        ranks = oracle.tree_ranks(v)
+        assert np.array_equal(out["tree"], x[ranks])
+        b = oracle.classify(keys, x)
+        assert np.array_equal(out["bucket"].astype(np.uint32), b)
+        assert np.array_equal(out["hist"], np.bincount(b, minlength=2 * v + 1).astype(np.uint32))
+        assert np.array_equal(out["perm"], np.argsort(b, kind="stable").astype(np.uint32))
+
+
+def test_tiny_degenerate(sorter):
+    for strs in ([b"a"], [b"b", b"a"], [b"", b""], [b"x"] * 3, [b"", b"a", b""], [b"abc", b"ab", b"abd"]):
+        assert_parity(sorter, W.from_list(strs), f"tiny {strs}")
+
+
+def test_empty_input(sorter):
+    from paper_1403_2056_amd import ssort
+    d = ssort.strings_to_device(W.from_list([]))
+    perm, lcp = sorter.sort(d)
+    torch.cuda.synchronize()
+    assert perm.numel() == 0 and lcp.numel() == 0
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_adversarial(sorter, seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 6000))
+    strs = adversarial(rng, n)
+    layout = "lengths" if seed % 3 == 1 else "csr"
+    assert_parity(sorter, W.from_list(strs, layout=layout, pad=3 if layout == "lengths" else 0), f"adv{seed}")
+
+
+def test_plain_small_config(sorter):
+    assert_parity(sorter, W.plain(131072, seed=1), "plain n=131072")
+
+
+def test_prefixes_scaled(sorter):
+    assert_parity(sorter, W.prefixes(1 << 18, seed=2, n_prefix=64), "prefixes 2^18")
+
+
+def test_suffixes_scaled(sorter):
+    assert_parity(sorter, W.suffixes(1 << 18, seed=3), "suffixes 2^18")
+
+
+def test_all_identical_large(sorter):
+    assert_parity(sorter, W.from_list([b"samestring"] * 200000), "identical 200000")
+
+
+def test_long_common_prefix(sorter):
+    rng = np.random.default_rng(7)
+    p = b"q" * 700
+    strs = [p + bytes(rng.integers(97, 101, size=rng.integers(0, 6)).astype(np.uint8)) for _ in range(100000)]
+    assert_parity(sorter, W.from_list(strs), "shared prefix 700")
+
+
+def test_determinism(sorter):
+    ss = W.plain(50000, seed=8)
+    a = gpu_sort(sorter, ss)
+    b = gpu_sort(sorter, ss)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_perm_only(sorter):
+    ss = W.plain(70000, seed=9)
+    p, _ = gpu_sort(sorter, ss, with_lcp=False)
+    rp, _ = oracle.sort(ss, with_lcp=False)
+    assert np.array_equal(p, rp)
+
+
+@pytest.mark.parametrize("v,k,tb", [(1, 4, 16), (3, 4, 64), (63, 8, 128), (127, 4, 512), (255, 8, 1024),
+                                    (255, 4, 64), (31, 8, 256)])
+def test_tunings_give_identical_results(v, k, tb):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_2056_amd import ssort
+    s = ssort.Sorter(0, v=v, keys_per_thread=k, base_threshold=tb)
+    s.set_wait_limit(10000)
+    assert_parity(s, W.plain(100000, seed=12), f"tuning v={v} k={k} tb={tb}")
+    assert_parity(s, W.suffixes(1 << 16, seed=13), f"tuning v={v} k={k} tb={tb} suffixes")
+
+
+def test_validate_reports_zero_byte():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_2056_amd import ssort
+    s = ssort.Sorter(0, flags=ssort.SSORT_VALIDATE)
+    ss = W.from_list([b"ab", b"a\x00b", b"c"])
+    s.sort(ssort.strings_to_device(ss))
+    torch.cuda.synchronize()
+    assert s.query_error() == 5
+
+
+def test_workspace_too_small(sorter):
+    from paper_1403_2056_amd import ssort
+    d = ssort.strings_to_device(W.plain(1000, seed=1))
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ssort.SsortError) as e:
+        sorter.sort(d, ws=ws)
+    assert e.value.code == 3
+
+
+def test_batched_small(sorter):
+    from paper_1403_2056_amd import ssort
+    ss, sb = W.batched(m=48, seed=15, lo=0, hi=11)
+    d = ssort.strings_to_device(ss)
+    sbt = torch.from_numpy(sb.view(np.int32)).cuda()
+    perm, lcp = sorter.sort_batched(d, sbt)
+    torch.cuda.synchronize()
+    assert sorter.query_error() == 0
+    p, h = ssort.to_numpy_u32(perm), ssort.to_numpy_u32(lcp)
+    strs = ss.strings()
+    for s in range(len(sb) - 1):
+        a, b = int(sb[s]), int(sb[s + 1])
+        sub = W.from_list(strs[a:b])
+        rp, rh = oracle.sort(sub)
+        assert np.array_equal(p[a:b], rp), s
+        assert np.array_equal(h[a:b], rh), s

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from paper_1403_2056_amd import workloads as W
+from tests.cases import adversarial
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -46,34 +47,11 @@ def test_exhaustive_tiny():
     assert count == 1 + 15 + 225 + 3375
 
 
-def _adversarial(rng, n):
-    kind = rng.integers(0, 7)
-    if kind == 0:       # heavy duplicates over a tiny alphabet
-        pool = [bytes(rng.integers(97, 99, size=rng.integers(0, 6)).astype(np.uint8)) for _ in range(5)]
-        return [pool[rng.integers(0, 5)] for _ in range(n)]
-    if kind == 1:       # keys ending exactly at 8 / 16 bytes, shared prefixes
-        base = bytes(rng.integers(65, 91, size=24).astype(np.uint8))
-        return [base[: rng.choice([7, 8, 9, 15, 16, 17, 24])] + bytes([rng.integers(65, 68)]) * rng.integers(0, 2)
-                for _ in range(n)]
-    if kind == 2:       # extreme bytes 0x01 and 0xFF
-        return [bytes(rng.choice([1, 2, 254, 255], size=rng.integers(0, 12)).astype(np.uint8)) for _ in range(n)]
-    if kind == 3:       # prefix chains
-        s = bytes(rng.integers(97, 123, size=40).astype(np.uint8))
-        return [s[: rng.integers(0, 41)] for _ in range(n)]
-    if kind == 4:       # suffixes of a tiny periodic text
-        t = (b"abaab" * 20)[: rng.integers(1, 100)]
-        return [t[i:] for i in range(len(t))][:n]
-    if kind == 5:       # empty strings mixed in
-        return [b"" if rng.random() < 0.3 else bytes(rng.integers(33, 127, size=rng.integers(1, 30)).astype(np.uint8))
-                for _ in range(n)]
-    return [bytes(rng.integers(1, 256, size=rng.integers(0, 40)).astype(np.uint8)) for _ in range(n)]
-
-
 @pytest.mark.parametrize("seed", range(40))
 def test_random_adversarial(seed):
     rng = np.random.default_rng(seed)
     n = int(rng.integers(0, 2000))
-    strs = _adversarial(rng, n)
+    strs = adversarial(rng, n)
     layout = "lengths" if seed % 3 == 1 else "csr"
     ss, perm, lcp = run(strs, layout=layout, pad=5 if layout == "lengths" else 0)
     assert (perm, lcp) == brute(strs)
