@@ -149,6 +149,16 @@ ssort_status ssort_set_wait_limit(ssort_ctx *ctx, uint32_t ms);
  * used for wait limits, out[3] HIP device index.  Host pointer, 4 entries. */
 ssort_status ssort_device_info(const ssort_ctx *ctx, uint64_t *out);
 
+/* Phase timing.  With enable = 1 every later sort on this context records
+ * HIP events on its stream around its phases (creating them here, the only
+ * allocation); ssort_phase_ms then returns, after the stream has been
+ * synchronised, the milliseconds of the last sort's phases:
+ * ms[0] initialisation and whole-GPU root step, ms[1] persistent workers
+ * (segment steps and base cases), ms[2] boundary LCPs, ms[3] whole sort.
+ * Host pointer, 4 entries.  Not for use under graph capture. */
+ssort_status ssort_profile(ssort_ctx *ctx, int enable);
+ssort_status ssort_phase_ms(ssort_ctx *ctx, float *ms);
+
 const char *ssort_strerror(ssort_status s);
 
 /* ---- one classification step with its intermediates (parity checks) ----

@@ -19,6 +19,8 @@ struct ssort_ctx {
     unsigned long long wall_khz;
     uint32_t wait_ms;
     void *last_ws;
+    int prof;
+    hipEvent_t ev[4];
 };
 
 namespace {
@@ -216,7 +218,35 @@ ssort_status ssort_create(int device, const ssort_tuning *t, ssort_ctx **out) {
     return SSORT_OK;
 }
 
-void ssort_destroy(ssort_ctx *ctx) { free(ctx); }
+void ssort_destroy(ssort_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->prof)
+        for (int i = 0; i < 4; ++i) hipEventDestroy(ctx->ev[i]);
+    free(ctx);
+}
+
+ssort_status ssort_profile(ssort_ctx *ctx, int enable) {
+    if (!ctx) return SSORT_EINVAL;
+    if (enable && !ctx->prof) {
+        for (int i = 0; i < 4; ++i)
+            if (hipEventCreate(&ctx->ev[i]) != hipSuccess) return SSORT_EDEVICE;
+        ctx->prof = 1;
+    } else if (!enable && ctx->prof) {
+        for (int i = 0; i < 4; ++i) hipEventDestroy(ctx->ev[i]);
+        ctx->prof = 0;
+    }
+    return SSORT_OK;
+}
+
+ssort_status ssort_phase_ms(ssort_ctx *ctx, float *ms) {
+    if (!ctx || !ms || !ctx->prof) return SSORT_EINVAL;
+    if (hipEventSynchronize(ctx->ev[3]) != hipSuccess) return SSORT_EDEVICE;
+    if (hipEventElapsedTime(&ms[0], ctx->ev[0], ctx->ev[1]) != hipSuccess) return SSORT_EDEVICE;
+    if (hipEventElapsedTime(&ms[1], ctx->ev[1], ctx->ev[2]) != hipSuccess) return SSORT_EDEVICE;
+    if (hipEventElapsedTime(&ms[2], ctx->ev[2], ctx->ev[3]) != hipSuccess) return SSORT_EDEVICE;
+    if (hipEventElapsedTime(&ms[3], ctx->ev[0], ctx->ev[3]) != hipSuccess) return SSORT_EDEVICE;
+    return SSORT_OK;
+}
 
 ssort_status ssort_get_tuning(const ssort_ctx *ctx, ssort_tuning *t) {
     if (!ctx || !t) return SSORT_EINVAL;
@@ -258,12 +288,16 @@ ssort_status ssort_sort(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_p
     if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
     Params P = make_params(ctx, in, out_perm, out_lcp, ws, L, 1, nullptr);
     const bool multi = in->n > ROOT_MULTI_MIN;
+    if (ctx->prof) hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, multi ? 0u : 1u,
                        (unsigned long long)L.cap);
     if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
     if (multi) launch_root(ctx, P, L.ntiles, 0, true, s);
+    if (ctx->prof) hipEventRecord(ctx->ev[1], s);
     launch_worker(ctx, P, worker_grid(ctx, in->n, multi ? NBMAX : 1), s);
+    if (ctx->prof) hipEventRecord(ctx->ev[2], s);
     if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
+    if (ctx->prof) hipEventRecord(ctx->ev[3], s);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
 }
@@ -280,11 +314,15 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
     Params P = make_params(ctx, flat, out_perm, out_lcp, ws, L, m, set_begin);
+    if (ctx->prof) hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_init, dim3(grid_for(std::max<uint64_t>(L.cap, m))), dim3(NT), 0, s, P, 2u,
                        (unsigned long long)L.cap);
     if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
+    if (ctx->prof) hipEventRecord(ctx->ev[1], s);
     launch_worker(ctx, P, worker_grid(ctx, flat->n, m), s);
+    if (ctx->prof) hipEventRecord(ctx->ev[2], s);
     if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
+    if (ctx->prof) hipEventRecord(ctx->ev[3], s);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
 }

@@ -67,6 +67,8 @@ _SIGS = {
     "ssort_set_wait_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "ssort_device_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "ssort_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ssort_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "ssort_phase_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "ssort_debug_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -150,6 +152,14 @@ class Sorter:
 
     def set_wait_limit(self, ms: int):
         _check(lib().ssort_set_wait_limit(self._h, ms), "ssort_set_wait_limit")
+
+    def profile(self, enable: bool = True):
+        _check(lib().ssort_profile(self._h, 1 if enable else 0), "ssort_profile")
+
+    def phase_ms(self) -> dict:
+        a = (ctypes.c_float * 4)()
+        _check(lib().ssort_phase_ms(self._h, a), "ssort_phase_ms")
+        return {"root": a[0], "worker": a[1], "seam": a[2], "total": a[3]}
 
     def device_info(self) -> dict:
         a = (ctypes.c_uint64 * 4)()
