@@ -100,6 +100,11 @@ typedef struct {
     uint64_t strings;
     uint64_t base_groups;
     uint64_t max_depth;
+    /* persistent-worker time per phase, summed over workgroups, in wall-clock
+     * ticks (ssort_device_info out[2] kHz): 0 waiting for work, 1 sample and
+     * tree, 2 classify and count, 3 redistribution, 4 child scheduling and
+     * identical buckets, 5 base case, 6 common-prefix extension, 7 other */
+    uint64_t phase_ticks[8];
 } ssort_stats_t;
 
 /* Create a context on HIP device `device` (the current device if < 0).

@@ -353,6 +353,7 @@ ssort_status ssort_stats(ssort_ctx *ctx, ssort_stats_t *out, void *stream) {
     out->strings = c.st_strings;
     out->base_groups = c.st_base;
     out->max_depth = c.st_maxdepth;
+    for (int k = 0; k < 8; ++k) out->phase_ticks[k] = c.ph[k];
     return SSORT_OK;
 }
 

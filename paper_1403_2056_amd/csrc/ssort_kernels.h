@@ -11,8 +11,12 @@ struct Ctl {
     unsigned long long pending;   // tasks enqueued or running, not finished
     unsigned long long error;     // bit mask of device errors
     unsigned long long st_segments, st_strings, st_base, st_maxdepth;
-    unsigned long long pad[8];
+    unsigned long long ph[8];     // worker time per phase, wall-clock ticks summed over workgroups
 };
+
+// worker phases timed on the device
+enum { PH_WAIT = 0, PH_SAMPLE = 1, PH_CLASSIFY = 2, PH_SCATTER = 3, PH_CHILDREN = 4, PH_BASE = 5,
+       PH_EXTEND = 6, PH_OTHER = 7 };
 
 enum : unsigned long long { ERR_TIMEOUT = 1, ERR_BOUNDS = 2, ERR_ZERO = 4, ERR_QUEUE = 8, ERR_INTERNAL = 16 };
 

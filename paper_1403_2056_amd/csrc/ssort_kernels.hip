@@ -118,6 +118,23 @@ __device__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, 
     __syncthreads();
 }
 
+// Length of the common prefix of strings a and b, known to agree on [0, from),
+// compared 8 bytes at a time and given up once it reaches `stop` (the caller
+// only needs values below it).  Equal words that end both strings mean the
+// strings are identical.
+__device__ __forceinline__ uint32_t lcp_from(const Params &P, uint64_t sta, uint32_t lna, uint64_t stb, uint32_t lnb,
+                                             uint32_t from, const volatile uint32_t *stop) {
+    uint32_t l = from;
+    for (;;) {
+        if (l >= *stop) return l;
+        const uint64_t ka = key_at(P.S.chars, P.S.nchars, sta, lna, l);
+        const uint64_t kb = key_at(P.S.chars, P.S.nchars, stb, lnb, l);
+        if (ka != kb) return l + (uint32_t)(__clzll(ka ^ kb) >> 3);
+        if ((ka & 0xFF) == 0) return min(lna, lnb);
+        l += 8;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // LCP-aware base case (semantics of LCP insertion sort, Algorithm 5: sorted
 // order, stable by input index, and the adjacent LCPs).  A chunk of up to C
@@ -175,9 +192,24 @@ __device__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const 
     int cur = 0;
     bool more = true;
     while (more) {
+        // every active class first jumps to its exact common prefix: each
+        // member is compared with the class's first member from the class
+        // depth on (instead of one round per 8 equal bytes)
+        for (uint32_t q = tid; q < M; q += NT)
+            if (B.act[q] && q == B.cst[q]) B.scr[q] = 0xFFFFFFFFu;
+        __syncthreads();
+        for (uint32_t q = tid; q < M; q += NT)
+            if (B.act[q] && q != B.cst[q]) {
+                const uint32_t c0 = B.cst[q];
+                const uint32_t e = B.ord[cur][q], f = B.ord[cur][c0];
+                const uint32_t l = lcp_from(P, B.st[f], B.ln[f], B.st[e], B.ln[e], B.d[e], &B.scr[c0]);
+                atomicMin(&B.scr[c0], l);
+            }
+        __syncthreads();
         for (uint32_t q = tid; q < M; q += NT)
             if (B.act[q]) {
                 const uint32_t e = B.ord[cur][q];
+                B.d[e] = B.scr[B.cst[q]];
                 B.key[e] = key_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], B.d[e]);
             }
         __syncthreads();
@@ -257,6 +289,9 @@ struct StepLDS {
     uint32_t nsmall, nlarge, nident, nchunk;
     unsigned long long best;
     unsigned long long qpos;
+    unsigned long long ph[8];     // this workgroup's time per phase (thread 0)
+    unsigned long long ph_last;
+    uint32_t ext_min;
     uint32_t tmp[NW];
     union {
         struct {
@@ -268,6 +303,17 @@ struct StepLDS {
         BaseLDS<C> base;
     } u;
 };
+
+// Charge the time since the last mark to phase i (thread 0 only; called
+// right after a barrier, so it measures the workgroup's progress).
+template <typename LDS>
+__device__ __forceinline__ void mark(LDS &L, int i) {
+    if (threadIdx.x == 0) {
+        const unsigned long long now = wall_clock64();
+        L.ph[i] += now - L.ph_last;
+        L.ph_last = now;
+    }
+}
 
 struct SmallGroups {   // groups = consecutive entries of the step's small-bucket list
     const uint32_t *hist, *bst, *cdep, *psz;
@@ -350,13 +396,34 @@ __device__ void finish_ident(const Params &P, const Rec *src, uint32_t start, ui
 template <int K, int C>
 __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const uint32_t begin = t.begin, S = t.size, h = t.depth, meta = t.meta;
+    const uint32_t begin = t.begin, S = t.size, meta = t.meta;
+    uint32_t h = t.depth;
     auto kload = [&](uint32_t e, uint32_t hh) -> uint64_t {
         const Rec r = load_rec(P, meta, begin + e);
         return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
     };
     select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, L.u.s.samp,
                      L.u.s.srt, L.u.s.fl, L.tmp, kload);
+    mark(L, PH_SAMPLE);
+    if (uni(L.sp.ndistinct) == 1 && (L.sp.x[0] & 0xFF) != 0) {
+        // Every sampled string has the same next 8 bytes: an equality chain.
+        // Instead of one classification step per 8 equal bytes, find the
+        // segment's exact common prefix (the minimum over its strings of the
+        // LCP with its first string) and classify there.
+        if (tid == 0) L.ext_min = 0xFFFFFFFFu;
+        __syncthreads();
+        const Rec f = load_rec(P, meta, begin);
+        for (uint32_t e = 1 + tid; e < S; e += NT) {
+            const Rec r = load_rec(P, meta, begin + e);
+            atomicMin(&L.ext_min, lcp_from(P, f.st, f.ln, r.st, r.ln, h, &L.ext_min));
+        }
+        __syncthreads();
+        h = uni(L.ext_min);
+        mark(L, PH_EXTEND);
+        select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, L.u.s.samp,
+                         L.u.s.srt, L.u.s.fl, L.tmp, kload);
+        mark(L, PH_SAMPLE);
+    }
     for (int b = tid; b < NBPAD; b += NT) L.hist[b] = 0;
     if (tid == 0) {
         __hip_atomic_fetch_add(&P.ctl->st_segments, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -392,6 +459,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
         }
     }
     __syncthreads();
+    mark(L, PH_CLASSIFY);
     for (int b = tid; b < NBPAD; b += NT) L.bst[b] = (uint32_t)b < nb ? L.hist[b] : 0u;
     __syncthreads();
     block_scan(L.bst, (int)nb, L.tmp, true, AddOp(), 0u);
@@ -417,6 +485,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
     // the redistributed records must be visible to every wave and every workgroup
     __threadfence();
     __syncthreads();
+    mark(L, PH_SCATTER);
 
     // ---- children (Algorithm 1 output: bucket i has common prefix h + h'_{i/2}
     // for even i, except the outer buckets which keep h, and h + 8 for odd i) ----
@@ -482,6 +551,8 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
         const uint32_t b = L.lident[k];
         finish_ident(P, out, begin + L.bst[b], L.hist[b], t.setbase);
     }
+    __syncthreads();
+    mark(L, PH_CHILDREN);
     // small buckets: base-case chunks of at most C strings, never splitting a group
     if (nsmall) {
         const uint32_t cap = (P.tbase * 2 <= (uint32_t)C) ? (uint32_t)C - P.tbase : 0u;
@@ -504,6 +575,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
         }
     }
     __syncthreads();
+    mark(L, PH_BASE);
     if (nlarge >= 1) {
         const uint32_t b = uni(L.llarge[keep]);
         t = Task{begin + uni(L.bst[b]), uni(L.hist[b]), uni(L.cdep[b]), cpar, t.setbase};
@@ -519,6 +591,8 @@ __device__ void run_task(const Params &P, Task t, StepLDS<K, C> &L) {
     if (t.meta & M_IDENT) {
         const Rec *src = (t.meta & M_PARITY) ? P.R1 : P.R0;
         finish_ident(P, src, t.begin, t.size, t.setbase);
+        __syncthreads();
+        mark(L, PH_CHILDREN);
         return;
     }
     if (t.size <= P.tbase) {
@@ -534,6 +608,7 @@ __device__ void run_task(const Params &P, Task t, StepLDS<K, C> &L) {
         if (threadIdx.x == 0)
             __hip_atomic_fetch_add(&P.ctl->st_base, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, 1, t.size, g);
+        mark(L, PH_BASE);
         return;
     }
     while (seg_step<K, C>(P, t, L)) {
@@ -547,6 +622,8 @@ __global__ __launch_bounds__(NT) void k_worker(Params P) {
     __shared__ int outcome[NW];
     if (P.ctl->error) return;
     const int w = threadIdx.x >> 6;
+    if (threadIdx.x < 8) L.ph[threadIdx.x] = 0;
+    if (threadIdx.x == 0) L.ph_last = wall_clock64();
     for (;;) {
         // a barrier between the previous task's thread-0 epilogue and this
         // claim keeps the two thread-0 regions from being merged across the
@@ -564,6 +641,7 @@ __global__ __launch_bounds__(NT) void k_worker(Params P) {
         int o = 1;
         for (int ww = 0; ww < NW; ++ww) o = min(o, outcome[ww]);
         o = (int)uni((uint32_t)o);
+        mark(L, PH_WAIT);
         if (o <= 0) break;
         const Task t{uni(s->begin), uni(s->size), uni(s->depth), uni(s->meta), uni(s->setbase)};
         __syncthreads();   // every wave has read the slot: hand it back to the ring
@@ -575,9 +653,13 @@ __global__ __launch_bounds__(NT) void k_worker(Params P) {
         }
         __threadfence();
         __syncthreads();
+        mark(L, PH_OTHER);
         if (threadIdx.x == 0)
             __hip_atomic_fetch_add(&P.ctl->pending, ~0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();
+    if (threadIdx.x < 8)
+        __hip_atomic_fetch_add(&P.ctl->ph[threadIdx.x], L.ph[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -612,6 +694,7 @@ __global__ void k_init(Params P, uint32_t mode, unsigned long long cap) {
         c->pending = nroot;
         c->error = 0;
         c->st_segments = c->st_strings = c->st_base = c->st_maxdepth = 0;
+        for (int k = 0; k < 8; ++k) c->ph[k] = 0;
         if (P.lcp && P.S.n) P.lcp[0] = 0;
     }
 }

@@ -45,7 +45,11 @@ class Tuning(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("segments", ctypes.c_uint64), ("strings", ctypes.c_uint64),
-                ("base_groups", ctypes.c_uint64), ("max_depth", ctypes.c_uint64)]
+                ("base_groups", ctypes.c_uint64), ("max_depth", ctypes.c_uint64),
+                ("phase_ticks", ctypes.c_uint64 * 8)]
+
+
+PHASES = ["wait", "sample", "classify", "scatter", "children", "base", "extend", "other"]
 
 
 _lib = None
@@ -218,7 +222,7 @@ class Sorter:
         st = Stats()
         _check(lib().ssort_stats(self._h, ctypes.byref(st), _stream(stream)), "ssort_stats")
         return {"segments": st.segments, "strings": st.strings, "base_groups": st.base_groups,
-                "max_depth": st.max_depth}
+                "max_depth": st.max_depth, "phase_ticks": dict(zip(PHASES, list(st.phase_ticks)))}
 
     def debug_step(self, s: DeviceStrings, depth: int = 0, stream=None) -> dict:
         torch = self._torch
