@@ -119,19 +119,26 @@ __device__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, 
 }
 
 // Length of the common prefix of strings a and b, known to agree on [0, from),
-// compared 8 bytes at a time and given up once it reaches `stop` (the caller
-// only needs values below it).  Equal words that end both strings mean the
-// strings are identical.
+// compared 32 bytes (four independent 8-byte loads per string) at a time and
+// given up once it reaches `stop` (the caller only needs values below it).
+// Equal words that end both strings mean the strings are identical.
 __device__ __forceinline__ uint32_t lcp_from(const Params &P, uint64_t sta, uint32_t lna, uint64_t stb, uint32_t lnb,
                                              uint32_t from, const volatile uint32_t *stop) {
     uint32_t l = from;
     for (;;) {
         if (l >= *stop) return l;
-        const uint64_t ka = key_at(P.S.chars, P.S.nchars, sta, lna, l);
-        const uint64_t kb = key_at(P.S.chars, P.S.nchars, stb, lnb, l);
-        if (ka != kb) return l + (uint32_t)(__clzll(ka ^ kb) >> 3);
-        if ((ka & 0xFF) == 0) return min(lna, lnb);
-        l += 8;
+        uint64_t ka[4], kb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ka[i] = key_at(P.S.chars, P.S.nchars, sta, lna, l + 8 * i);
+            kb[i] = key_at(P.S.chars, P.S.nchars, stb, lnb, l + 8 * i);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (ka[i] != kb[i]) return l + 8 * i + (uint32_t)(__clzll(ka[i] ^ kb[i]) >> 3);
+            if ((ka[i] & 0xFF) == 0) return min(lna, lnb);
+        }
+        l += 32;
     }
 }
 
@@ -190,11 +197,13 @@ __device__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const 
     if (tid == 0) B.any = 0;
     __syncthreads();
     int cur = 0;
-    bool more = true;
+    bool more = true, first = true;
     while (more) {
-        // every active class first jumps to its exact common prefix: each
-        // member is compared with the class's first member from the class
-        // depth on (instead of one round per 8 equal bytes)
+        // after the first round every active class holds equal keys: it first
+        // jumps to its exact common prefix, each member compared with the
+        // class's first member from the class depth on (instead of one round
+        // per 8 equal bytes)
+        if (!first) {
         for (uint32_t q = tid; q < M; q += NT)
             if (B.act[q] && q == B.cst[q]) B.scr[q] = 0xFFFFFFFFu;
         __syncthreads();
@@ -207,9 +216,13 @@ __device__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const 
             }
         __syncthreads();
         for (uint32_t q = tid; q < M; q += NT)
+            if (B.act[q]) B.d[B.ord[cur][q]] = B.scr[B.cst[q]];
+        __syncthreads();
+        }
+        first = false;
+        for (uint32_t q = tid; q < M; q += NT)
             if (B.act[q]) {
                 const uint32_t e = B.ord[cur][q];
-                B.d[e] = B.scr[B.cst[q]];
                 B.key[e] = key_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], B.d[e]);
             }
         __syncthreads();
