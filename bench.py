@@ -45,6 +45,166 @@ def dist_bytes(lens_sorted: np.ndarray, lcp: np.ndarray) -> np.ndarray:
     return np.minimum(lens_sorted.astype(np.int64), 1 + np.maximum(left, right))
 
 
+def bench_batched(args):
+    """Batched form: 4096 independent sets (sizes 2^U(6,18), geometric lengths
+    with mean 24, 95 printable bytes) sorted by one graph-captured launch,
+    against the same sets sorted one at a time (one ssort_sort per set, each
+    synchronised).  The tuning is the autotuner's choice for this workload."""
+    import torch
+    from paper_1403_2056_amd import autotune, ssort, workloads
+    t0 = time.time()
+    ss, sb = workloads.batched(m=args.sets, seed=5)
+    n = ss.n
+    print(f"[bench] batched: {args.sets} sets, n={n}, N={len(ss.chars)} in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    d = ssort.strings_to_device(ss)
+    sbt = torch.from_numpy(sb.view(np.int32)).cuda()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    tun = autotune.lookup(arch, "batched", n)
+    table = None
+    if tun is None or args.retune:
+        # tune on the first quarter of the sets (same size distribution)
+        q = args.sets // 4
+        nq = int(sb[q])
+        dq = ssort.DeviceStrings(d.chars, d.nchars, d.offsets[: nq + 1], None, nq, 0)
+        sbq = sbt[: q + 1]
+
+        def factory(c):
+            s = ssort.Sorter(0, **c)
+            g = ssort.Graph(s, dq, set_begin=sbq)
+
+            def run():
+                g.launch()
+                g.stream.synchronize()
+            run._keep = (s, g)
+            return run
+        tun, table = autotune.tune(factory, log=lambda m: print(m, file=sys.stderr, flush=True))
+        autotune.store(arch, "batched", n, dict(tun))
+    sorter = ssort.Sorter(0, **tun)
+    g = ssort.Graph(sorter, d, set_begin=sbt)
+    for _ in range(args.warmup):
+        g.launch()
+    g.stream.synchronize()
+    assert sorter.query_error(g.stream) == 0
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        g.launch()
+    g.stream.synchronize()
+    t_graph = (time.perf_counter() - t1) / args.steps
+    assert sorter.query_error(g.stream) == 0
+    # one set at a time, each sort synchronised before the next
+    plain = ssort.Sorter(0, **tun)
+    perm1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    lcp1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = plain.workspace(int(np.diff(sb.astype(np.int64)).max()))
+    views = []
+    for k in range(args.sets):
+        a, b = int(sb[k]), int(sb[k + 1])
+        views.append((ssort.DeviceStrings(d.chars, d.nchars, d.offsets[a: b + 1], None, b - a, 0), a, b))
+    for v, a, b in views[: min(64, len(views))]:
+        plain.sort(v, out_perm=perm1[a:b], out_lcp=lcp1[a:b], ws=ws)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for v, a, b in views:
+        plain.sort(v, out_perm=perm1[a:b], out_lcp=lcp1[a:b], ws=ws)
+        torch.cuda.synchronize()
+    t_one = time.perf_counter() - t2
+    same_perm = bool(torch.equal(g.perm[:n], perm1))
+    same_lcp = bool(torch.equal(g.lcp[:n], lcp1))
+    out = {"metric": "strings/sec batched (one graph launch) vs one-at-a-time", "value": round(n / t_graph, 1),
+           "unit": "strings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t_graph * 1000, 3), "higher_is_better": True, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": f"batched: {args.sets} sets of 2^U(6,18) strings, geometric lengths mean 24, "
+                                  "95 printable bytes", "n": n, "N": int(len(ss.chars)), "tuning": tun},
+           "one_at_a_time_ms": round(t_one * 1000, 3), "one_at_a_time_strings_per_s": round(n / t_one, 1),
+           "batched_vs_one_at_a_time": round(t_one / t_graph, 2),
+           "identical_to_one_at_a_time": same_perm and same_lcp}
+    if table:
+        out["autotune"] = [{**c, "ms": round(ms, 3)} for c, ms in table]
+    if not args.no_cpu:
+        import oracle
+        rng = np.random.default_rng(0)
+        p = g.perm[:n].cpu().numpy().view(np.uint32)
+        h = g.lcp[:n].cpu().numpy().view(np.uint32)
+        strs = None
+        bad = 0
+        for k in rng.choice(args.sets, size=min(32, args.sets), replace=False):
+            a, b = int(sb[k]), int(sb[k + 1])
+            sub = workloads.StringSet(ss.chars, ss.offsets[a: b + 1].copy(), None, 0, b - a, {})
+            rp, rh = oracle.sort(sub)
+            bad += int(not (np.array_equal(p[a:b], rp) and np.array_equal(h[a:b], rh)))
+        out["oracle_checked_sets"] = 32 - bad
+        t3 = time.perf_counter()
+        done = 0
+        for k in range(args.sets):
+            a, b = int(sb[k]), int(sb[k + 1])
+            oracle.sort(workloads.StringSet(ss.chars, ss.offsets[a: b + 1].copy(), None, 0, b - a, {}))
+            done += b - a
+            if time.perf_counter() - t3 > 20:
+                break
+        tc = time.perf_counter() - t3
+        out["cpu_baseline"] = {"value": round(done / tc, 1), "unit": "strings/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {done} strings of the batch, set by set"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Serving form: a Poisson stream of jobs (sizes 2^U(4,20) strings, each
+    drawn from the plain / long-prefix / suffix generators), admitted by a
+    64 GB resident-memory budget with continuous batching, against the same
+    jobs one at a time (one slot, one job per launch)."""
+    from paper_1403_2056_amd import ssort, workloads
+    rng = np.random.default_rng(7)
+    jobs = []
+    t0 = time.time()
+    for _ in range(args.jobs):
+        nj = int(np.floor(2.0 ** rng.uniform(4, 20)))
+        jobs.append(workloads.mixed_job(rng, nj))
+    ntot = sum(j.n for j in jobs)
+    print(f"[bench] serve: {args.jobs} jobs, {ntot} strings, generated in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    def run(slots, max_jobs, rate):
+        srv = ssort.Server(0, budget_bytes=args.budget_gb << 30, slots=slots, max_jobs_per_launch=max_jobs,
+                           stage_bytes=512 << 20)
+        for j in jobs[:8]:                     # warm-up
+            srv.wait(srv.submit(j))
+        lat = []
+        t_start = time.perf_counter()
+        tickets = []
+        next_t = t_start
+        for j in jobs:
+            if rate:
+                next_t += rng.exponential(1.0 / rate)
+                while time.perf_counter() < next_t:
+                    pass
+            tickets.append(srv.submit(j))
+        for t in tickets:
+            _, _, info = srv.wait(t)
+            lat.append(info["latency_ms"])
+        el = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        lat = np.array(lat)
+        return {"seconds": round(el, 3), "jobs_per_s": round(len(jobs) / el, 1),
+                "strings_per_s": round(ntot / el, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3), "launches": st["launches"],
+                "max_jobs_per_launch": st["max_jobs_per_launch"]}
+    one = run(1, 1, 0)                        # one job at a time, saturated
+    mu1 = one["jobs_per_s"]
+    sat = run(4, 4096, 4 * mu1)               # offered load 4x the one-at-a-time rate
+    lat = run(4, 4096, 0.7 * mu1)             # offered load the one-at-a-time server sustains
+    one_lat = run(1, 1, 0.7 * mu1)
+    out = {"metric": "served jobs/s and p50/p99 latency, continuous batching vs one-job-at-a-time",
+           "value": sat["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "u8", "data": "synthetic",
+           "config": {"workload": f"{args.jobs} Poisson jobs, sizes 2^U(4,20), plain/long-prefix/suffix mix",
+                      "strings": ntot, "budget_gb": args.budget_gb},
+           "served_saturated": sat, "served_at_0.7x": lat, "one_at_a_time": one, "one_at_a_time_at_0.7x": one_lat,
+           "throughput_vs_one_at_a_time": round(sat["jobs_per_s"] / mu1, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,11 +217,20 @@ def main():
     ap.add_argument("--v", type=int, default=255)
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--tb", type=int, default=128)
+    ap.add_argument("--mode", choices=["plain", "batched", "serve"], default="plain")
+    ap.add_argument("--sets", type=int, default=4096)
+    ap.add_argument("--retune", action="store_true")
+    ap.add_argument("--jobs", type=int, default=600)
+    ap.add_argument("--budget-gb", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.mode == "batched":
+        return bench_batched(args)
+    if args.mode == "serve":
+        return bench_serve(args)
 
     import torch
     from paper_1403_2056_amd import ssort, workloads

@@ -183,6 +183,83 @@ ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t 
                               uint16_t *bucket, uint32_t *hist, uint32_t *perm, void *ws,
                               size_t ws_bytes, void *stream);
 
+/* ---- graph-captured launch (the batched form) ----
+ * Capture one sort (set_begin == NULL: ssort_sort of `in`; else
+ * ssort_sort_batched of m sets) with fixed buffers into a HIP graph on
+ * `stream` (which must not be the legacy default stream) and instantiate it;
+ * ssort_graph_launch replays the whole sort as one graph launch.  The graph
+ * holds no memset nodes: the queue and counters are reset by a kernel in
+ * every replay.  Buffers must stay valid while the graph exists. */
+typedef struct ssort_graph ssort_graph;
+ssort_status ssort_graph_create(ssort_ctx *ctx, const ssort_strings *in, const uint32_t *set_begin, uint32_t m,
+                                uint32_t *out_perm, uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream,
+                                ssort_graph **out);
+ssort_status ssort_graph_launch(ssort_graph *g, void *stream);
+void ssort_graph_destroy(ssort_graph *g);
+
+/* ---- serving: a request loop with continuous batching on one GPU ----
+ * The server owns a resident HBM arena of `hbm_budget` bytes (allocated at
+ * creation) and `slots` launch slots (streams with pinned staging buffers; 4
+ * matches the hardware queues of one process).  A scheduler thread admits
+ * waiting jobs in FIFO order while their packed device buffers (characters,
+ * descriptors, outputs, sort workspace) fit into the arena and the per-launch
+ * limits, sorts each admitted group with one batched launch sequence
+ * (ssort_sort_batched) on a free slot, and copies the results back; jobs that
+ * arrive while others run join the next free slot, so work overlaps on the
+ * device.  Each job's result is identical to sorting it alone. */
+typedef struct ssort_server ssort_server;
+
+/* One job: HOST pointers, owned by the caller until ssort_server_wait returns.
+ *  chars/nchars/offsets/n/flags  as in ssort_strings (CSR n+1 offsets, or n
+ *                                starts with SSORT_TO_END), in host memory
+ *  out_perm  host uint32[n], written on completion
+ *  out_lcp   host uint32[n] or NULL */
+typedef struct {
+    const uint8_t *chars;
+    uint64_t nchars;
+    const uint64_t *offsets;
+    uint32_t n;
+    uint32_t flags;
+    uint32_t *out_perm;
+    uint32_t *out_lcp;
+} ssort_job;
+
+typedef struct {
+    uint64_t ticket;
+    int status;          /* ssort_status of the job */
+    double latency_ms;   /* submission to completion */
+    double queue_ms;     /* submission to launch */
+} ssort_result;
+
+/* Optional limits (0 = default): pinned staging bytes per slot and direction
+ * (256 MiB), jobs per launch (4096), strings per launch (2^26). */
+typedef struct {
+    size_t stage_bytes;
+    uint32_t max_jobs_per_launch;
+    uint64_t max_strings_per_launch;
+} ssort_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, launches, jobs_launched, max_jobs_per_launch;
+    uint64_t arena_used, waiting;
+} ssort_server_stats_t;
+
+/* Allocates the arena (hipMalloc), pinned staging (hipHostMalloc), streams and
+ * contexts; t and cfg may be NULL.  SSORT_ENOMEM if any allocation fails. */
+ssort_status ssort_server_create(int device, size_t hbm_budget, uint32_t slots, const ssort_tuning *t,
+                                 const ssort_server_config *cfg, ssort_server **out);
+/* Queue a job.  SSORT_EBUSY if it could never fit (larger than the arena or a
+ * staging buffer); otherwise it waits for memory, FIFO. */
+ssort_status ssort_server_submit(ssort_server *srv, const ssort_job *job, uint64_t *ticket);
+/* Wait for a job (timeout_ms < 0: forever); returns its status and forgets
+ * the ticket.  SSORT_ETIMEOUT if still running, SSORT_ENOTFOUND if unknown or
+ * cancelled. */
+ssort_status ssort_server_wait(ssort_server *srv, uint64_t ticket, int timeout_ms, ssort_result *res);
+/* Remove a job that is still waiting for admission. */
+ssort_status ssort_server_cancel(ssort_server *srv, uint64_t ticket);
+ssort_status ssort_server_stats(ssort_server *srv, ssort_server_stats_t *out);
+void ssort_server_destroy(ssort_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 
 #include "ssort.h"
 #include "ssort_kernels.hip"
+#include "ssort_serve.hip"
 
 using namespace ssd;
 
@@ -117,7 +118,7 @@ void launch_root(const ssort_ctx *c, const Params &P, uint32_t ntiles, uint32_t 
     hipLaunchKernelGGL(k_root_sample, dim3(1), dim3(NT), 0, s, P, depth);
     if (c->tun.keys_per_thread == 4) hipLaunchKernelGGL((k_root_classify<4>), dim3(ntiles), dim3(NT), 0, s, P, depth);
     else hipLaunchKernelGGL((k_root_classify<8>), dim3(ntiles), dim3(NT), 0, s, P, depth);
-    hipLaunchKernelGGL(k_root_colscan, dim3(NBMAX), dim3(NT), 0, s, P);
+    hipLaunchKernelGGL(k_root_colscan, dim3((NBMAX + CS_B - 1) / CS_B), dim3(NT), 0, s, P);
     if (c->tun.keys_per_thread == 4) hipLaunchKernelGGL((k_root_scatter<4>), dim3(ntiles), dim3(NT), 0, s, P);
     else hipLaunchKernelGGL((k_root_scatter<8>), dim3(ntiles), dim3(NT), 0, s, P);
     if (schedule) hipLaunchKernelGGL(k_root_schedule, dim3(1), dim3(NT), 0, s, P, depth);
@@ -221,7 +222,7 @@ ssort_status ssort_create(int device, const ssort_tuning *t, ssort_ctx **out) {
 void ssort_destroy(ssort_ctx *ctx) {
     if (!ctx) return;
     if (ctx->prof)
-        for (int i = 0; i < 4; ++i) hipEventDestroy(ctx->ev[i]);
+        for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ctx->ev[i]);
     free(ctx);
 }
 
@@ -232,7 +233,7 @@ ssort_status ssort_profile(ssort_ctx *ctx, int enable) {
             if (hipEventCreate(&ctx->ev[i]) != hipSuccess) return SSORT_EDEVICE;
         ctx->prof = 1;
     } else if (!enable && ctx->prof) {
-        for (int i = 0; i < 4; ++i) hipEventDestroy(ctx->ev[i]);
+        for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ctx->ev[i]);
         ctx->prof = 0;
     }
     return SSORT_OK;
@@ -288,16 +289,16 @@ ssort_status ssort_sort(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_p
     if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
     Params P = make_params(ctx, in, out_perm, out_lcp, ws, L, 1, nullptr);
     const bool multi = in->n > ROOT_MULTI_MIN;
-    if (ctx->prof) hipEventRecord(ctx->ev[0], s);
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, multi ? 0u : 1u,
                        (unsigned long long)L.cap);
     if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
     if (multi) launch_root(ctx, P, L.ntiles, 0, true, s);
-    if (ctx->prof) hipEventRecord(ctx->ev[1], s);
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[1], s);
     launch_worker(ctx, P, worker_grid(ctx, in->n, multi ? NBMAX : 1), s);
-    if (ctx->prof) hipEventRecord(ctx->ev[2], s);
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[2], s);
     if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
-    if (ctx->prof) hipEventRecord(ctx->ev[3], s);
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[3], s);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
 }
@@ -314,15 +315,15 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
     Params P = make_params(ctx, flat, out_perm, out_lcp, ws, L, m, set_begin);
-    if (ctx->prof) hipEventRecord(ctx->ev[0], s);
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_init, dim3(grid_for(std::max<uint64_t>(L.cap, m))), dim3(NT), 0, s, P, 2u,
                        (unsigned long long)L.cap);
     if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
-    if (ctx->prof) hipEventRecord(ctx->ev[1], s);
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[1], s);
     launch_worker(ctx, P, worker_grid(ctx, flat->n, m), s);
-    if (ctx->prof) hipEventRecord(ctx->ev[2], s);
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[2], s);
     if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
-    if (ctx->prof) hipEventRecord(ctx->ev[3], s);
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[3], s);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
 }
@@ -375,6 +376,60 @@ ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t 
                        hist, perm);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
+}
+
+struct ssort_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+ssort_status ssort_graph_create(ssort_ctx *ctx, const ssort_strings *in, const uint32_t *set_begin, uint32_t m,
+                                uint32_t *out_perm, uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream,
+                                ssort_graph **out) {
+    if (!ctx || !out || !stream) return SSORT_EINVAL;
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    const int prof = ctx->prof;
+    ctx->prof = 0;   // no event records inside the graph
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        ctx->prof = prof;
+        return SSORT_EDEVICE;
+    }
+    ssort_status rc = set_begin ? ssort_sort_batched(ctx, in, set_begin, m, out_perm, out_lcp, ws, ws_bytes, stream)
+                                : ssort_sort(ctx, in, out_perm, out_lcp, ws, ws_bytes, stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    ctx->prof = prof;
+    if (rc != SSORT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) return SSORT_EDEVICE;
+    ssort_graph *G = (ssort_graph *)calloc(1, sizeof(ssort_graph));
+    if (!G) {
+        (void)hipGraphDestroy(g);
+        return SSORT_ENOMEM;
+    }
+    G->graph = g;
+    if (hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        free(G);
+        return SSORT_EDEVICE;
+    }
+    *out = G;
+    return SSORT_OK;
+}
+
+ssort_status ssort_graph_launch(ssort_graph *g, void *stream) {
+    if (!g) return SSORT_EINVAL;
+    return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
+}
+
+void ssort_graph_destroy(ssort_graph *g) {
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    free(g);
 }
 
 }  // extern "C"

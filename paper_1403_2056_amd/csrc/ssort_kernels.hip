@@ -800,33 +800,50 @@ __global__ __launch_bounds__(NT) void k_root_classify(Params P, uint32_t depth) 
         if (valid) P.bkt[e] = (uint16_t)m;
     }
     __syncthreads();
-    for (uint32_t b = tid; b < nb; b += NT) P.hist[(size_t)b * P.ntiles + blockIdx.x] = hist[b];
+    for (uint32_t b = tid; b < nb; b += NT) P.hist[(size_t)blockIdx.x * NBPAD + b] = hist[b];
 }
 
-// Exclusive scan over the tiles of one bucket (bucket-major layout), giving
-// every (tile, bucket) pair its offset inside the bucket; totals per bucket.
+// Exclusive scan over the tiles, per bucket, of the tile histograms (stored
+// tile-major: one contiguous row of counters per tile), giving every (tile,
+// bucket) pair its offset inside the bucket, and the bucket totals.  A
+// workgroup owns 16 buckets; thread t handles bucket 16g + t%16 over the tile
+// range t/16, so 16 neighbouring threads read one 64-byte run of a row.
+constexpr int CS_B = 16;
+constexpr int CS_R = NT / CS_B;
 __global__ __launch_bounds__(NT) void k_root_colscan(Params P) {
-    __shared__ uint32_t tmp[NW];
-    __shared__ uint32_t part[NT];
+    __shared__ uint32_t part[CS_R][CS_B];
     if (P.ctl->error) return;
-    const uint32_t b = blockIdx.x;
-    if (b >= P.gsplit->nb) return;
-    uint32_t *row = P.hist + (size_t)b * P.ntiles;
+    const uint32_t nb = uni(P.gsplit->nb);
+    const uint32_t b = blockIdx.x * CS_B + (threadIdx.x % CS_B);
+    const uint32_t r = threadIdx.x / CS_B;
     const uint32_t T = P.ntiles;
-    const uint32_t per = (T + NT - 1) / NT;
-    const uint32_t lo = threadIdx.x * per, hi = min(T, lo + per);
+    const uint32_t per = (T + CS_R - 1) / CS_R;
+    const uint32_t lo = min(T, r * per), hi = min(T, lo + per);
     uint32_t s = 0;
-    for (uint32_t i = lo; i < hi; ++i) s += row[i];
-    part[threadIdx.x] = s;
+    if (b < nb)
+        for (uint32_t i = lo; i < hi; ++i) s += P.hist[(size_t)i * NBPAD + b];
+    part[r][threadIdx.x % CS_B] = s;
     __syncthreads();
-    const uint32_t total = block_scan(part, NT, tmp, true, AddOp(), 0u);
-    uint32_t run = part[threadIdx.x];
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t x = row[i];
-        row[i] = run;
-        run += x;
+    if (threadIdx.x < CS_B) {
+        uint32_t run = 0;
+        for (int k = 0; k < CS_R; ++k) {
+            const uint32_t x = part[k][threadIdx.x];
+            part[k][threadIdx.x] = run;
+            run += x;
+        }
+        const uint32_t bb = blockIdx.x * CS_B + threadIdx.x;
+        if (bb < nb) P.totals[bb] = run;
     }
-    if (threadIdx.x == 0) P.totals[b] = total;
+    __syncthreads();
+    if (b < nb) {
+        uint32_t run = part[r][threadIdx.x % CS_B];
+        for (uint32_t i = lo; i < hi; ++i) {
+            uint32_t *c = &P.hist[(size_t)i * NBPAD + b];
+            const uint32_t x = *c;
+            *c = run;
+            run += x;
+        }
+    }
 }
 
 template <int K>
@@ -847,7 +864,7 @@ __global__ __launch_bounds__(NT) void k_root_scatter(Params P) {
     for (uint32_t b = tid; b < NBPAD; b += NT) L.run[b] = b < nb ? P.totals[b] : 0u;
     __syncthreads();
     block_scan(L.run, (int)nb, L.tmp, true, AddOp(), 0u);
-    for (uint32_t b = tid; b < nb; b += NT) L.run[b] += P.hist[(size_t)b * P.ntiles + blockIdx.x];
+    for (uint32_t b = tid; b < nb; b += NT) L.run[b] += P.hist[(size_t)blockIdx.x * NBPAD + b];
     __syncthreads();
     const uint32_t c0 = blockIdx.x * (uint32_t)(NT * K);
     Rec r[K];

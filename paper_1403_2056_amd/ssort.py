@@ -52,6 +52,28 @@ class Stats(ctypes.Structure):
 PHASES = ["wait", "sample", "classify", "scatter", "children", "base", "extend", "other"]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("chars", ctypes.c_void_p), ("nchars", ctypes.c_uint64), ("offsets", ctypes.c_void_p),
+                ("n", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("out_perm", ctypes.c_void_p),
+                ("out_lcp", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int), ("latency_ms", ctypes.c_double),
+                ("queue_ms", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("stage_bytes", ctypes.c_size_t), ("max_jobs_per_launch", ctypes.c_uint32),
+                ("max_strings_per_launch", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("jobs_launched", ctypes.c_uint64), ("max_jobs_per_launch", ctypes.c_uint64),
+                ("arena_used", ctypes.c_uint64), ("waiting", ctypes.c_uint64)]
+
+
 _lib = None
 
 # every entry point declared in include/ssort.h, with its ctypes signature
@@ -73,6 +95,18 @@ _SIGS = {
     "ssort_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ssort_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "ssort_phase_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "ssort_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_void_p,
+                                          ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "ssort_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ssort_graph_destroy": (None, [ctypes.c_void_p]),
+    "ssort_server_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p,
+                                           ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    "ssort_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]),
+    "ssort_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(Result)]),
+    "ssort_server_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ssort_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "ssort_server_destroy": (None, [ctypes.c_void_p]),
     "ssort_debug_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -250,6 +284,94 @@ class Sorter:
         out["tree"] = out["tree"][:v]
         out["hist"] = out["hist"][:2 * v + 1]
         return out
+
+
+class Graph:
+    """A captured sort (plain or batched) replayed with one graph launch."""
+
+    def __init__(self, sorter, s: DeviceStrings, set_begin=None, with_lcp=True, stream=None):
+        torch = sorter._torch
+        dev = f"cuda:{sorter.device}"
+        n = s.n
+        m = 1 if set_begin is None else set_begin.numel() - 1
+        self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self.lcp = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if with_lcp else None
+        self.ws = torch.empty(sorter.workspace_bytes(n, m), dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self._keep = (s, set_begin)
+        st = s.struct()
+        h = ctypes.c_void_p()
+        with torch.cuda.stream(self.stream):
+            _check(lib().ssort_graph_create(sorter._h, ctypes.byref(st), _ptr(set_begin), m, _ptr(self.perm),
+                                            _ptr(self.lcp), _ptr(self.ws), self.ws.numel(),
+                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                   "ssort_graph_create")
+        self._h = h
+        self.n = n
+
+    def launch(self):
+        _check(lib().ssort_graph_launch(self._h, ctypes.c_void_p(self.stream.cuda_stream)), "ssort_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ssort_graph_destroy(self._h)
+            self._h = None
+
+
+class Server:
+    """Request loop with continuous batching (host-side jobs)."""
+
+    def __init__(self, device=0, budget_bytes=1 << 30, slots=4, v=255, keys_per_thread=4, base_threshold=128,
+                 stage_bytes=0, max_jobs_per_launch=0, max_strings_per_launch=0):
+        self.tuning = Tuning(v, keys_per_thread, base_threshold, 0)
+        cfg = ServerConfig(stage_bytes, max_jobs_per_launch, max_strings_per_launch)
+        h = ctypes.c_void_p()
+        _check(lib().ssort_server_create(device, budget_bytes, slots, ctypes.byref(self.tuning),
+                                         ctypes.byref(cfg), ctypes.byref(h)), "ssort_server_create")
+        self._h = h
+        self._jobs = {}
+
+    def submit(self, ss, with_lcp=True) -> int:
+        chars = np.ascontiguousarray(ss.chars, dtype=np.uint8)
+        if chars.size == 0:
+            chars = np.zeros(1, np.uint8)
+        off = np.ascontiguousarray(ss.offsets, dtype=np.uint64)
+        if ss.lengths is not None:
+            raise ValueError("server jobs use CSR offsets or SSORT_TO_END starts")
+        perm = np.empty(max(ss.n, 1), dtype=np.uint32)
+        lcp = np.empty(max(ss.n, 1), dtype=np.uint32) if with_lcp else None
+        job = Job(chars.ctypes.data, len(ss.chars), off.ctypes.data, ss.n, ss.flags, perm.ctypes.data,
+                  lcp.ctypes.data if with_lcp else None)
+        t = ctypes.c_uint64()
+        _check(lib().ssort_server_submit(self._h, ctypes.byref(job), ctypes.byref(t)), "ssort_server_submit")
+        self._jobs[t.value] = (chars, off, perm, lcp, ss.n)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        r = Result()
+        rc = lib().ssort_server_wait(self._h, ticket, timeout_ms, ctypes.byref(r))
+        chars, off, perm, lcp, n = self._jobs.pop(ticket)
+        _check(rc, "ssort_server_wait")
+        return perm[:n], (lcp[:n] if lcp is not None else None), {"latency_ms": r.latency_ms, "queue_ms": r.queue_ms}
+
+    def cancel(self, ticket: int) -> bool:
+        ok = lib().ssort_server_cancel(self._h, ticket) == 0
+        if ok:
+            self._jobs.pop(ticket, None)
+        return ok
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().ssort_server_stats(self._h, ctypes.byref(st)), "ssort_server_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ssort_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def to_numpy_u32(t) -> np.ndarray:
