@@ -115,7 +115,7 @@ struct MaxOp { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { re
 // each thread owns a run of consecutive entries.  tmp needs NW entries.
 // Returns the total.  Must be called by all threads; includes barriers.
 template <typename Op>
-__device__ uint32_t block_scan(uint32_t *a, int len, uint32_t *tmp, bool exclusive, Op op, uint32_t ident) {
+__device__ __forceinline__ uint32_t block_scan(uint32_t *a, int len, uint32_t *tmp, bool exclusive, Op op, uint32_t ident) {
     const int tid = threadIdx.x;
     const int per = (len + NT - 1) / NT;
     const int lo = tid * per;
@@ -146,11 +146,21 @@ __device__ uint32_t block_scan(uint32_t *a, int len, uint32_t *tmp, bool exclusi
 // Splitter set of one classification step (LDS or global copy).
 struct Split {
     uint64_t tree[VMAX + 1];   // level order, tree[1..v]
-    uint64_t x[VMAX + 1];      // in-order (sorted) splitters x[0..v)
     uint8_t hl[VMAX + 1];      // hl[l] = lcp(x[l-1], x[l]) in bytes, hl[0] = hl[v] = 0
     uint8_t zr[VMAX + 1];      // zr[l] = x[l] ends its string (last byte zero)
     uint32_t v, d, nb, nbits, ndistinct, pad[3];
 };
+
+// Level-order node of the splitter with in-order rank r in a perfect tree of
+// depth d: with r+1 = (2p+1)·2^k the node sits k levels above the leaves, at
+// position p of its level (the rank-to-tree conversion of the second
+// equality-check variant in the implementation details of S5).
+__device__ __forceinline__ uint32_t node_of_rank(uint32_t r, uint32_t d) {
+    const uint32_t k = __builtin_ctz(r + 1);
+    return (1u << (d - 1 - k)) + ((r + 1) >> (k + 1));
+}
+
+__device__ __forceinline__ uint64_t splitter(const Split &sp, uint32_t r) { return sp.tree[node_of_rank(r, sp.d)]; }
 
 // Bucket of key c: descend the level-order tree going right when c > t_i,
 // then l = i - (v+1) counts the splitters below c; bucket 2l, plus one when
@@ -161,7 +171,7 @@ __device__ __forceinline__ uint32_t classify(uint64_t c, const Split &sp) {
     for (int l = 0; l < DMAX; ++l)
         if (l < (int)sp.d) i = 2 * i + (c > sp.tree[i] ? 1u : 0u);
     const uint32_t l = i - (sp.v + 1);
-    return 2 * l + ((l < sp.v && sp.x[l] == c) ? 1u : 0u);
+    return 2 * l + ((l < sp.v && splitter(sp, l) == c) ? 1u : 0u);
 }
 
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
@@ -179,7 +189,7 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 // tree, the splitter LCPs (xor + count leading zeros) and the end-of-string
 // flags.  `samp`, `srt` need SAMPLE_MAX+1 entries, `fl` SAMPLE_MAX+1, tmp NW.
 template <typename Load>
-__device__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
+__device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
                                  uint64_t *samp, uint64_t *srt, uint32_t *fl, uint32_t *tmp, Load load) {
     const int tid = threadIdx.x;
     const uint32_t a = size < (uint32_t)(2 * (vmax + 1) - 1) ? size : (uint32_t)(2 * (vmax + 1) - 1);
@@ -218,12 +228,11 @@ __device__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t 
         v = vmax;
         d = 31 - __clz(vmax + 1);
     }
-    for (uint32_t j = tid; j < v; j += NT) {
-        uint32_t src;
-        if (U <= vmax) src = j < U ? j : U - 1;
-        else src = (uint32_t)(((uint64_t)(j + 1) * U) / (v + 1));
-        sp.x[j] = samp[src];
-    }
+    // splitter of in-order rank j: samp[xsrc(j)]
+    auto xsrc = [&](uint32_t j) -> uint32_t {
+        if (U <= vmax) return j < U ? j : U - 1;
+        return (uint32_t)(((uint64_t)(j + 1) * U) / (v + 1));
+    };
     if (tid == 0) {
         sp.v = v;
         sp.d = d;
@@ -238,16 +247,16 @@ __device__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t 
         const uint32_t delta = 31 - __clz(j);
         const uint32_t p = j - (1u << delta);
         const uint32_t r = ((2 * p + 1) << (d - 1 - delta)) - 1;
-        sp.tree[j] = sp.x[r];
+        sp.tree[j] = samp[xsrc(r)];
     }
     for (uint32_t l = tid; l <= v; l += NT) {
         uint32_t hl = 0;
         if (l > 0 && l < v) {
-            const uint64_t z = sp.x[l - 1] ^ sp.x[l];
+            const uint64_t z = samp[xsrc(l - 1)] ^ samp[xsrc(l)];
             hl = z ? (uint32_t)(__clzll(z) >> 3) : 8u;
         }
         sp.hl[l] = (uint8_t)hl;
-        sp.zr[l] = (l < v && (sp.x[l] & 0xFF) == 0) ? 1 : 0;
+        sp.zr[l] = (l < v && (samp[xsrc(l)] & 0xFF) == 0) ? 1 : 0;
     }
     __syncthreads();
 }

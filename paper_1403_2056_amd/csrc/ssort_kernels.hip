@@ -52,22 +52,23 @@ __device__ __forceinline__ unsigned long long add_agent(unsigned long long *p, u
 // of bucket b and is advanced past the chunk.
 template <int K>
 struct ScatterLDS {
-    uint32_t wcnt[NW][NBPAD];
-    uint32_t tot[NBPAD];
+    uint16_t wcnt[NW][NBPAD];   // per wave and bucket, at most 64*K per chunk
+    uint16_t tot[NBPAD];        // per bucket in the chunk, at most NT*K
     uint32_t cs[NBPAD];
     Rec rec[NT * K];
     uint16_t b[NT * K];
+    uint32_t run[NBPAD];        // next output position per bucket (a step's own)
 };
 
 template <int K>
-__device__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, const uint32_t (&m)[K],
+__device__ __forceinline__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, const uint32_t (&m)[K],
                               const Rec (&r)[K], uint32_t cnt, uint32_t *run, Rec *out, uint32_t nlim,
                               unsigned long long *err) {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const uint32_t nb = uni(sp.nb);
     const int nbits = (int)uni(sp.nbits);
-    uint32_t *wc = &L.wcnt[0][0];
-    for (int i = tid; i < NW * NBPAD; i += NT) wc[i] = 0;
+    uint32_t *wc = (uint32_t *)&L.wcnt[0][0];
+    for (int i = tid; i < NW * NBPAD / 2; i += NT) wc[i] = 0;
     __syncthreads();
     uint32_t rk[K];
 #pragma unroll
@@ -79,7 +80,7 @@ __device__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, 
         const uint32_t base = L.wcnt[w][mj];
         rk[j] = base + mbcnt(mask);
         __builtin_amdgcn_wave_barrier();
-        if (lane == 63 - (int)__clzll(mask)) L.wcnt[w][mj] = base + (uint32_t)__popcll(mask);
+        if (lane == 63 - (int)__clzll(mask)) L.wcnt[w][mj] = (uint16_t)(base + (uint32_t)__popcll(mask));
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
@@ -88,10 +89,10 @@ __device__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, 
 #pragma unroll
         for (int ww = 0; ww < NW; ++ww) {
             const uint32_t t = L.wcnt[ww][b];
-            L.wcnt[ww][b] = c;
+            L.wcnt[ww][b] = (uint16_t)c;
             c += t;
         }
-        L.tot[b] = c;
+        L.tot[b] = (uint16_t)c;
         L.cs[b] = c;
     }
     __syncthreads();
@@ -168,7 +169,7 @@ struct BaseLDS {
 // Group accessor: group g of the chunk has global start gstart(g), size
 // gsize(g), common depth gdepth(g) and chunk-local exclusive prefix gpre(g).
 template <int C, typename G>
-__device__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const Rec *src, uint32_t setbase,
+__device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const Rec *src, uint32_t setbase,
                            uint32_t ng, uint32_t M, const G &grp) {
     const int tid = threadIdx.x;
     auto find = [&](uint32_t q) -> uint32_t {
@@ -183,16 +184,31 @@ __device__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const 
         const uint32_t g = find(q);
         return grp.gstart(g) + (q - grp.gpre(g));
     };
-    for (uint32_t q = tid; q < M; q += NT) {
-        const uint32_t g = find(q);
-        const Rec r = src[grp.gstart(g) + (q - grp.gpre(g))];
-        B.st[q] = r.st;
-        B.ln[q] = r.ln;
-        B.id[q] = r.id;
-        B.d[q] = grp.gdepth(g);
-        B.cst[q] = (uint16_t)grp.gpre(g);
-        B.ord[0][q] = (uint16_t)q;
-        B.act[q] = grp.gsize(g) >= 2 ? 1 : 0;
+    constexpr int PER = (C + NT - 1) / NT;   // positions per thread
+    {
+        uint32_t gg[PER];
+        Rec rr[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t q = tid + u * NT;
+            if (q < M) {
+                gg[u] = find(q);
+                rr[u] = src[grp.gstart(gg[u]) + (q - grp.gpre(gg[u]))];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t q = tid + u * NT;
+            if (q >= M) continue;
+            const uint32_t g = gg[u];
+            B.st[q] = rr[u].st;
+            B.ln[q] = rr[u].ln;
+            B.id[q] = rr[u].id;
+            B.d[q] = grp.gdepth(g);
+            B.cst[q] = (uint16_t)grp.gpre(g);
+            B.ord[0][q] = (uint16_t)q;
+            B.act[q] = grp.gsize(g) >= 2 ? 1 : 0;
+        }
     }
     if (tid == 0) B.any = 0;
     __syncthreads();
@@ -220,11 +236,22 @@ __device__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const 
         __syncthreads();
         }
         first = false;
-        for (uint32_t q = tid; q < M; q += NT)
-            if (B.act[q]) {
-                const uint32_t e = B.ord[cur][q];
-                B.key[e] = key_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], B.d[e]);
+        {
+            uint64_t kk[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t q = tid + u * NT;
+                if (q < M && B.act[q]) {
+                    const uint32_t e = B.ord[cur][q];
+                    kk[u] = key_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], B.d[e]);
+                }
             }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t q = tid + u * NT;
+                if (q < M && B.act[q]) B.key[B.ord[cur][q]] = kk[u];
+            }
+        }
         __syncthreads();
         for (uint32_t q = tid; q < M; q += NT) {
             const uint32_t e = B.ord[cur][q];
@@ -292,8 +319,6 @@ struct StepLDS {
     Split sp;
     uint32_t hist[NBPAD];     // strings per bucket
     uint32_t bst[NBPAD];      // bucket start, relative to the segment
-    uint32_t run[NBPAD];      // next output position per bucket (absolute)
-    uint32_t cdep[NBPAD];     // common depth of each child bucket
     uint32_t psz[NBPAD + 1];  // exclusive size prefix over the small buckets
     uint16_t lsmall[NBPAD];
     uint16_t llarge[NBPAD];
@@ -328,13 +353,23 @@ __device__ __forceinline__ void mark(LDS &L, int i) {
     }
 }
 
+// Common depth of bucket b's strings after a step at depth h (Algorithm 1's
+// output): h for the outer buckets b_0 and b_2v, h plus the splitter LCP for
+// the other range buckets, h + 8 for equality buckets.
+__device__ __forceinline__ uint32_t child_depth(const Split &sp, uint32_t h, uint32_t b) {
+    if (b & 1) return h + 8;
+    if (b == 0 || b == sp.nb - 1) return h;
+    return h + sp.hl[b >> 1];
+}
+
 struct SmallGroups {   // groups = consecutive entries of the step's small-bucket list
-    const uint32_t *hist, *bst, *cdep, *psz;
+    const uint32_t *hist, *bst, *psz;
     const uint16_t *lsmall;
-    uint32_t k0, begin, pre0;
+    const Split *sp;
+    uint32_t k0, begin, pre0, h;
     __device__ uint32_t gstart(uint32_t g) const { return begin + bst[lsmall[k0 + g]]; }
     __device__ uint32_t gsize(uint32_t g) const { return hist[lsmall[k0 + g]]; }
-    __device__ uint32_t gdepth(uint32_t g) const { return cdep[lsmall[k0 + g]]; }
+    __device__ uint32_t gdepth(uint32_t g) const { return child_depth(*sp, h, lsmall[k0 + g]); }
     __device__ uint32_t gpre(uint32_t g) const { return psz[k0 + g] - pre0; }
 };
 
@@ -358,7 +393,7 @@ __device__ __forceinline__ unsigned long long uni64(unsigned long long x) {
 // fence when the task is there.  Returns 1 (task ready), 0 (queue drained:
 // nothing pending, so nothing can be enqueued any more) or -1 (device error or
 // the wait limit, by wall clock or by poll count).
-__device__ int poll_slot(const Params &P, Slot *s, unsigned long long pos) {
+__device__ __forceinline__ int poll_slot(const Params &P, Slot *s, unsigned long long pos) {
     const unsigned long long t0 = wall_clock64();
     for (unsigned long long it = 0;; ++it) {
         if (uni64(ld_rlx(&s->seq)) == pos + 1) {
@@ -380,7 +415,7 @@ __device__ int poll_slot(const Params &P, Slot *s, unsigned long long pos) {
 // attempt, no waiting: the ring is sized so that the slot's previous occupant
 // (pos - capacity) has long been consumed; if it has not, the sort fails with
 // a device error instead of overwriting it.
-__device__ void publish(const Params &P, unsigned long long pos, const Task &t) {
+__device__ __forceinline__ void publish(const Params &P, unsigned long long pos, const Task &t) {
     Slot *s = &P.ring[pos & P.ring_mask];
     if (ld_rlx(&s->seq) != pos) {
         __hip_atomic_fetch_or(&P.ctl->error, ERR_QUEUE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -396,7 +431,7 @@ __device__ void publish(const Params &P, unsigned long long pos, const Task &t) 
 
 // Identical strings (an equality bucket whose splitter ends the string):
 // already in input-index order; lcp between them is their length.
-__device__ void finish_ident(const Params &P, const Rec *src, uint32_t start, uint32_t cnt, uint32_t setbase) {
+__device__ __forceinline__ void finish_ident(const Params &P, const Rec *src, uint32_t start, uint32_t cnt, uint32_t setbase) {
     for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
         const Rec r = src[start + i];
         P.perm[start + i] = r.id - setbase;
@@ -407,7 +442,7 @@ __device__ void finish_ident(const Params &P, const Rec *src, uint32_t start, ui
 // One classification step of a segment by one workgroup.  Returns true when
 // `t` has been replaced by a child segment this workgroup continues with.
 template <int K, int C>
-__device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
+__device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const uint32_t begin = t.begin, S = t.size, meta = t.meta;
     uint32_t h = t.depth;
@@ -418,7 +453,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
     select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, L.u.s.samp,
                      L.u.s.srt, L.u.s.fl, L.tmp, kload);
     mark(L, PH_SAMPLE);
-    if (uni(L.sp.ndistinct) == 1 && (L.sp.x[0] & 0xFF) != 0) {
+    if (uni(L.sp.ndistinct) == 1 && (splitter(L.sp, 0) & 0xFF) != 0) {
         // Every sampled string has the same next 8 bytes: an equality chain.
         // Instead of one classification step per 8 equal bytes, find the
         // segment's exact common prefix (the minimum over its strings of the
@@ -426,9 +461,47 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
         if (tid == 0) L.ext_min = 0xFFFFFFFFu;
         __syncthreads();
         const Rec f = load_rec(P, meta, begin);
-        for (uint32_t e = 1 + tid; e < S; e += NT) {
-            const Rec r = load_rec(P, meta, begin + e);
-            atomicMin(&L.ext_min, lcp_from(P, f.st, f.ln, r.st, r.ln, h, &L.ext_min));
+        uint64_t fk[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fk[i] = key_at(P.S.chars, P.S.nchars, f.st, f.ln, h + 8 * i);
+        // four strings per thread at a time: their records, then their first
+        // 32 bytes (16 independent loads), then the comparisons
+        for (uint32_t e0 = 1 + tid; e0 < S; e0 += 4 * NT) {
+            Rec r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e0 + u * NT < S) r[u] = load_rec(P, meta, begin + e0 + u * NT);
+            uint64_t k[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    k[u][i] = (e0 + u * NT < S) ? key_at(P.S.chars, P.S.nchars, r[u].st, r[u].ln, h + 8 * i) : 0;
+            uint32_t res = 0xFFFFFFFFu;
+            uint32_t more = 0;   // strings equal to the reference on all 32 bytes
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bool done = e0 + u * NT >= S;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (done) continue;
+                    if (k[u][i] != fk[i]) {
+                        res = min(res, h + 8 * i + (uint32_t)(__clzll(k[u][i] ^ fk[i]) >> 3));
+                        done = true;
+                    } else if ((fk[i] & 0xFF) == 0) {
+                        res = min(res, min(f.ln, r[u].ln));
+                        done = true;
+                    }
+                }
+                if (!done) more |= 1u << u;
+            }
+            while (more) {
+                const uint32_t u = __builtin_ctz(more);
+                more &= more - 1;
+                const Rec q = load_rec(P, meta, begin + e0 + u * NT);
+                res = min(res, lcp_from(P, f.st, f.ln, q.st, q.ln, h + 32, &L.ext_min));
+            }
+            atomicMin(&L.ext_min, res);
         }
         __syncthreads();
         h = uni(L.ext_min);
@@ -476,7 +549,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
     for (int b = tid; b < NBPAD; b += NT) L.bst[b] = (uint32_t)b < nb ? L.hist[b] : 0u;
     __syncthreads();
     block_scan(L.bst, (int)nb, L.tmp, true, AddOp(), 0u);
-    for (int b = tid; b < NBPAD; b += NT) L.run[b] = begin + L.bst[b];
+    for (int b = tid; b < NBPAD; b += NT) L.u.sc.run[b] = begin + L.bst[b];
     __syncthreads();
     const bool to1 = out_is_r1(meta);
     Rec *out = to1 ? P.R1 : P.R0;
@@ -493,7 +566,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
                 m[j] = nb;
             }
         }
-        scatter_chunk<K>(L.u.sc, L.tmp, L.sp, m, r, min(CK, S - c0), L.run, out, P.S.n, &P.ctl->error);
+        scatter_chunk<K>(L.u.sc, L.tmp, L.sp, m, r, min(CK, S - c0), L.u.sc.run, out, P.S.n, &P.ctl->error);
     }
     // the redistributed records must be visible to every wave and every workgroup
     __threadfence();
@@ -515,7 +588,6 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
         if (cnt) {
             const uint32_t l = b >> 1;
             const bool odd = b & 1;
-            L.cdep[b] = odd ? h + 8 : ((b == 0 || b == nb - 1) ? h : h + L.sp.hl[l]);
             if (P.lcp && st > 0) P.lcp[begin + st] = SEAM | h;
             if (odd && L.sp.zr[l]) {
                 L.lident[atomicAdd(&L.nident, 1u)] = (uint16_t)b;
@@ -553,7 +625,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
         for (uint32_t k = tid; k < nlarge; k += NT) {
             if (k == keep) continue;
             const uint32_t b = L.llarge[k];
-            Task c{begin + L.bst[b], L.hist[b], L.cdep[b], cpar, t.setbase};
+            Task c{begin + L.bst[b], L.hist[b], child_depth(L.sp, h, b), cpar, t.setbase};
             publish(P, L.qpos + (k < keep ? k : k - 1), c);
         }
     }
@@ -583,7 +655,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
             __hip_atomic_fetch_add(&P.ctl->st_base, (unsigned long long)nsmall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (uint32_t c = 0; c < nchunk; ++c) {
             const uint32_t k0 = uni(L.cfirst[c]), k1 = uni(L.cfirst[c + 1]);
-            SmallGroups g{L.hist, L.bst, L.cdep, L.psz, L.lsmall, k0, begin, L.psz[k0]};
+            SmallGroups g{L.hist, L.bst, L.psz, L.lsmall, &L.sp, k0, begin, L.psz[k0], h};
             base_chunk<C>(P, L.u.base, L.tmp, out, t.setbase, k1 - k0, uni(L.psz[k1] - L.psz[k0]), g);
         }
     }
@@ -591,7 +663,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
     mark(L, PH_BASE);
     if (nlarge >= 1) {
         const uint32_t b = uni(L.llarge[keep]);
-        t = Task{begin + uni(L.bst[b]), uni(L.hist[b]), uni(L.cdep[b]), cpar, t.setbase};
+        t = Task{begin + uni(L.bst[b]), uni(L.hist[b]), child_depth(L.sp, h, b), cpar, t.setbase};
         __syncthreads();
         return true;
     }
@@ -599,7 +671,7 @@ __device__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
 }
 
 template <int K, int C>
-__device__ void run_task(const Params &P, Task t, StepLDS<K, C> &L) {
+__device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> &L) {
     if (t.size == 0) return;
     if (t.meta & M_IDENT) {
         const Rec *src = (t.meta & M_PARITY) ? P.R1 : P.R0;
@@ -629,7 +701,7 @@ __device__ void run_task(const Params &P, Task t, StepLDS<K, C> &L) {
 }
 
 template <int K, int C>
-__global__ __launch_bounds__(NT) void k_worker(Params P) {
+__global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
     __shared__ StepLDS<K, C> L;
     __shared__ unsigned long long claim;
     __shared__ int outcome[NW];
@@ -961,7 +1033,7 @@ __global__ void k_debug_dump(Params P, uint32_t depth, uint64_t *keys, uint64_t 
     }
     if (blockIdx.x == 0) {
         for (uint32_t j = threadIdx.x; j < 256; j += NT) {
-            split[j] = j < sp->v ? sp->x[j] : 0;
+            split[j] = j < sp->v ? splitter(*sp, j) : 0;
             tree[j] = (j < sp->v) ? sp->tree[j + 1] : 0;
         }
         for (uint32_t b = threadIdx.x; b < NBPAD; b += NT) hist[b] = b < sp->nb ? P.totals[b] : 0;
