@@ -45,7 +45,8 @@ struct Layout {
 Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     Layout L;
     const uint32_t K = c->tun.keys_per_thread;
-    L.ntiles = n ? (uint32_t)((n + (uint64_t)NT * K - 1) / ((uint64_t)NT * K)) : 0u;
+    const uint64_t tile = (uint64_t)NT * K * ROOT_CHUNKS;
+    L.ntiles = n ? (uint32_t)((n + tile - 1) / tile) : 0u;
     // queued tasks are disjoint segments of more than base_threshold strings
     // plus the root tasks; twice that bound leaves every slot's previous
     // occupant consumed long before the slot is reused

@@ -20,6 +20,7 @@ constexpr int NBMAX = 2 * VMAX + 1;     // 511 buckets
 constexpr int NBPAD = 512;
 constexpr int SAMPLE_MAX = 2 * (VMAX + 1) - 1;   // oversampling factor 2
 constexpr int CH = 1024;                // base-case chunk (strings held in LDS)
+constexpr int ROOT_CHUNKS = 8;          // chunks of NT*K strings per whole-GPU root-step tile
 constexpr uint32_t SEAM = 0x80000000u;  // lcp slot still holds a separation depth
 constexpr uint32_t TO_END = 1u;
 

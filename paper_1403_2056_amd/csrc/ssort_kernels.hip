@@ -849,27 +849,31 @@ __global__ __launch_bounds__(NT) void k_root_classify(Params P, uint32_t depth) 
     __syncthreads();
     const uint32_t n = P.S.n, nb = uni(sp.nb);
     const int nbits = (int)uni(sp.nbits);
-    const uint32_t c0 = blockIdx.x * (uint32_t)(NT * K);
-    Rec r[K];
+    // one tile = ROOT_CHUNKS chunks of NT*K strings, classified chunk by chunk
+    for (uint32_t ch = 0; ch < ROOT_CHUNKS; ++ch) {
+        const uint32_t c0 = (blockIdx.x * ROOT_CHUNKS + ch) * (uint32_t)(NT * K);
+        if (c0 >= n) break;
+        Rec r[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-        if (e < n) r[j] = make_rec(P.S, e);
-    }
-    uint64_t k[K];
+        for (int j = 0; j < K; ++j) {
+            const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+            if (e < n) r[j] = make_rec(P.S, e);
+        }
+        uint64_t k[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-        k[j] = e < n ? key_at(P.S.chars, P.S.nchars, r[j].st, r[j].ln, depth) : 0;
-    }
+        for (int j = 0; j < K; ++j) {
+            const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+            k[j] = e < n ? key_at(P.S.chars, P.S.nchars, r[j].st, r[j].ln, depth) : 0;
+        }
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-        const bool valid = e < n;
-        const uint32_t m = valid ? classify(k[j], sp) : nb;
-        const uint64_t mask = match_any(m, nbits);
-        if (valid && lane == 63 - (int)__clzll(mask)) atomicAdd(&hist[m], (uint32_t)__popcll(mask));
-        if (valid) P.bkt[e] = (uint16_t)m;
+        for (int j = 0; j < K; ++j) {
+            const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+            const bool valid = e < n;
+            const uint32_t m = valid ? classify(k[j], sp) : nb;
+            const uint64_t mask = match_any(m, nbits);
+            if (valid && lane == 63 - (int)__clzll(mask)) atomicAdd(&hist[m], (uint32_t)__popcll(mask));
+            if (valid) P.bkt[e] = (uint16_t)m;
+        }
     }
     __syncthreads();
     for (uint32_t b = tid; b < nb; b += NT) P.hist[(size_t)blockIdx.x * NBPAD + b] = hist[b];
@@ -892,8 +896,10 @@ __global__ __launch_bounds__(NT) void k_root_colscan(Params P) {
     const uint32_t per = (T + CS_R - 1) / CS_R;
     const uint32_t lo = min(T, r * per), hi = min(T, lo + per);
     uint32_t s = 0;
-    if (b < nb)
+    if (b < nb) {
+#pragma unroll 8
         for (uint32_t i = lo; i < hi; ++i) s += P.hist[(size_t)i * NBPAD + b];
+    }
     part[r][threadIdx.x % CS_B] = s;
     __syncthreads();
     if (threadIdx.x < CS_B) {
@@ -938,20 +944,23 @@ __global__ __launch_bounds__(NT) void k_root_scatter(Params P) {
     block_scan(L.run, (int)nb, L.tmp, true, AddOp(), 0u);
     for (uint32_t b = tid; b < nb; b += NT) L.run[b] += P.hist[(size_t)blockIdx.x * NBPAD + b];
     __syncthreads();
-    const uint32_t c0 = blockIdx.x * (uint32_t)(NT * K);
-    Rec r[K];
-    uint32_t m[K];
+    for (uint32_t ch = 0; ch < ROOT_CHUNKS; ++ch) {
+        const uint32_t c0 = (blockIdx.x * ROOT_CHUNKS + ch) * (uint32_t)(NT * K);
+        if (c0 >= n) break;
+        Rec r[K];
+        uint32_t m[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-        if (e < n) {
-            r[j] = make_rec(P.S, e);
-            m[j] = P.bkt[e];
-        } else {
-            m[j] = nb;
+        for (int j = 0; j < K; ++j) {
+            const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
+            if (e < n) {
+                r[j] = make_rec(P.S, e);
+                m[j] = P.bkt[e];
+            } else {
+                m[j] = nb;
+            }
         }
+        scatter_chunk<K>(L.sc, L.tmp, L.sp, m, r, min((uint32_t)(NT * K), n - c0), L.run, P.R1, n, &P.ctl->error);
     }
-    scatter_chunk<K>(L.sc, L.tmp, L.sp, m, r, min((uint32_t)(NT * K), n - c0), L.run, P.R1, n, &P.ctl->error);
 }
 
 // Children of the root step become the first tasks of the queue.
@@ -1043,6 +1052,30 @@ __global__ void k_debug_dump(Params P, uint32_t depth, uint64_t *keys, uint64_t 
             info[2] = sp->ndistinct;
             info[3] = 0;
         }
+    }
+}
+
+// Packing of a server batch: job k's strings are rows set_begin[k] ..
+// set_begin[k+1] of the flat space; its characters start at char_base and its
+// raw offsets (CSR n+1, or n starts for suffixes of its text) at raw_base.
+struct PackJob {
+    unsigned long long char_base, raw_base, off0, nchars;
+    uint32_t n, flags;
+};
+
+__global__ void k_pack(const PackJob *jobs, const uint32_t *set_begin, uint32_t m, const unsigned long long *raw,
+                       unsigned long long *starts, uint32_t *lengths, uint32_t n) {
+    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        uint32_t lo = 0, hi = m;                 // last job with set_begin <= i
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (set_begin[mid] <= i) lo = mid; else hi = mid;
+        }
+        const PackJob J = jobs[lo];
+        const uint32_t j = i - set_begin[lo];
+        const unsigned long long o = raw[J.raw_base + j];
+        starts[i] = J.char_base + (o - J.off0);
+        lengths[i] = (J.flags & TO_END) ? (uint32_t)(J.nchars - o) : (uint32_t)(raw[J.raw_base + j + 1] - o);
     }
 }
 

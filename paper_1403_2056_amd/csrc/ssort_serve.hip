@@ -16,6 +16,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <functional>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -51,8 +52,79 @@ struct LaunchSlot {
 
 size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Small persistent pool for the host-side copies into pinned staging.
+class CopyPool {
+  public:
+    explicit CopyPool(int n) {
+        for (int i = 0; i < n; ++i) th_.emplace_back([this] { work(); });
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    // run f(0..count-1) on the pool and the calling thread; returns when done
+    void run(size_t count, const std::function<void(size_t)> &f) {
+        if (count == 0) return;
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            f_ = &f;
+            count_ = count;
+            next_ = 0;
+            left_ = count;
+            ++gen_;
+        }
+        cv_.notify_all();
+        drain();
+        std::unique_lock<std::mutex> lk(m_);
+        done_.wait(lk, [&] { return left_ == 0; });
+        f_ = nullptr;
+    }
+
+  private:
+    void drain() {
+        for (;;) {
+            size_t i;
+            const std::function<void(size_t)> *f;
+            {
+                std::lock_guard<std::mutex> lk(m_);
+                if (!f_ || next_ >= count_) return;
+                i = next_++;
+                f = f_;
+            }
+            (*f)(i);
+            std::lock_guard<std::mutex> lk(m_);
+            if (--left_ == 0) done_.notify_all();
+        }
+    }
+    void work() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return stop_ || (gen_ != seen && f_ && next_ < count_); });
+                if (stop_) return;
+                seen = gen_;
+            }
+            drain();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(size_t)> *f_ = nullptr;
+    size_t count_ = 0, next_ = 0, left_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
+uint64_t job_raw_entries(const ssort_job &j) { return (j.flags & SSORT_TO_END) ? j.n : (uint64_t)j.n + 1; }
+
 struct PackLayout {
-    size_t chars, starts, lengths, setb, perm, lcp, ws, total, stage_in, out_bytes;
+    size_t chars, raw, jobs, starts, lengths, setb, perm, lcp, ws, total, stage_in, out_bytes;
     uint64_t nchars, n;
     uint32_t m;
 };
@@ -71,6 +143,7 @@ struct ssort_server {
     uint64_t max_strings = 0;
     uint8_t *arena = nullptr;
     ssd::Admission *adm = nullptr;
+    CopyPool *pool = nullptr;
     std::vector<LaunchSlot> slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -92,11 +165,16 @@ struct ssort_server {
         size_t ws = 0;
         ssort_workspace_bytes(slots[0].ctx, (uint32_t)n, m ? m : 1, &ws);
         size_t off = 0;
+        // copied in: characters, raw offsets, job table, set boundaries
         L.chars = off; off = a256(off + nchars + 8);
-        L.starts = off; off = a256(off + 8 * n);
-        L.lengths = off; off = a256(off + 4 * n);
+        L.raw = off; off = a256(off + 8 * (n + m));
+        L.jobs = off; off = a256(off + sizeof(ssd::PackJob) * m);
         L.setb = off; off = a256(off + 4 * (m + 1));
         L.stage_in = off;
+        // built on the device
+        L.starts = off; off = a256(off + 8 * n);
+        L.lengths = off; off = a256(off + 4 * n);
+        // copied out
         L.perm = off; off = a256(off + 4 * n);
         L.lcp = off; off = a256(off + 4 * n);
         L.out_bytes = off - L.perm;
@@ -113,15 +191,25 @@ struct ssort_server {
         return sizes(nc, n, (uint32_t)ts.size());
     }
 
-    // Launch the admitted jobs on slot s (called with mu held).
+    // Launch the admitted jobs on slot s (called with mu held): pack their
+    // characters and raw offsets into the slot's pinned staging (copy pool),
+    // copy in, build start/length descriptors on the device, sort the batch,
+    // copy the permutations and LCP arrays out, record the completion event.
     void launch(LaunchSlot &s, const std::vector<uint64_t> &ts, const PackLayout &L) {
         uint8_t *dev = arena + s.arena_off;
         uint8_t *in = s.stage_in;
-        uint64_t *starts = (uint64_t *)(in + L.starts);
-        uint32_t *lens = (uint32_t *)(in + L.lengths);
+        uint64_t *raw = (uint64_t *)(in + L.raw);
+        ssd::PackJob *jt = (ssd::PackJob *)(in + L.jobs);
         uint32_t *setb = (uint32_t *)(in + L.setb);
-        uint64_t cbase = 0, sbase = 0;
+        uint64_t cbase = 0, sbase = 0, rbase = 0;
         s.set_begin.assign(L.m + 1, 0);
+        struct Piece { const void *src; void *dst; size_t len; };
+        std::vector<Piece> pieces;
+        const size_t PIECE = (size_t)8 << 20;
+        auto add = [&](const void *src, void *dst, size_t len) {
+            for (size_t o = 0; o < len; o += PIECE)
+                pieces.push_back({(const uint8_t *)src + o, (uint8_t *)dst + o, std::min(PIECE, len - o)});
+        };
         for (uint32_t k = 0; k < L.m; ++k) {
             JobRec &r = jobs[ts[k]];
             const ssort_job &j = r.job;
@@ -129,26 +217,34 @@ struct ssort_server {
             r.t_start = clk::now();
             const uint64_t nc = job_nchars(j);
             const uint64_t o0 = (j.flags & SSORT_TO_END) ? 0 : (j.n ? j.offsets[0] : 0);
-            memcpy(in + L.chars + cbase, j.chars + o0, nc);
-            for (uint32_t i = 0; i < j.n; ++i) {
-                starts[sbase + i] = cbase + (j.offsets[i] - o0);
-                lens[sbase + i] = (j.flags & SSORT_TO_END) ? (uint32_t)(j.nchars - j.offsets[i])
-                                                           : (uint32_t)(j.offsets[i + 1] - j.offsets[i]);
-            }
+            add(j.chars + o0, in + L.chars + cbase, nc);
+            const uint64_t re = j.n ? job_raw_entries(j) : 0;
+            add(j.offsets, raw + rbase, 8 * re);
+            jt[k] = ssd::PackJob{cbase, rbase, o0, j.nchars, j.n, j.flags};
             setb[k] = (uint32_t)sbase;
             s.set_begin[k] = (uint32_t)sbase;
             cbase += nc;
             sbase += j.n;
+            rbase += re;
         }
         setb[L.m] = (uint32_t)sbase;
         s.set_begin[L.m] = (uint32_t)sbase;
         s.jobs = ts;
+        pool->run(pieces.size(), [&](size_t i) { memcpy(pieces[i].dst, pieces[i].src, pieces[i].len); });
         hipError_t ce = hipMemcpyAsync(dev, in, L.stage_in, hipMemcpyHostToDevice, s.stream);
+        if (ce == hipSuccess && L.n) {
+            const uint32_t grid = (uint32_t)std::min<uint64_t>((L.n + ssd::NT - 1) / ssd::NT, 4096);
+            hipLaunchKernelGGL(ssd::k_pack, dim3(grid), dim3(ssd::NT), 0, s.stream, (const ssd::PackJob *)(dev + L.jobs),
+                               (const uint32_t *)(dev + L.setb), L.m, (const unsigned long long *)(dev + L.raw),
+                               (unsigned long long *)(dev + L.starts), (uint32_t *)(dev + L.lengths), (uint32_t)L.n);
+            ce = hipGetLastError();
+        }
         ssort_strings flat{dev + L.chars, L.nchars, (const uint64_t *)(dev + L.starts),
                            (const uint32_t *)(dev + L.lengths), (uint32_t)L.n, 0};
-        ssort_status rc = ssort_sort_batched(s.ctx, &flat, (const uint32_t *)(dev + L.setb), L.m,
-                                             (uint32_t *)(dev + L.perm), (uint32_t *)(dev + L.lcp), dev + L.ws,
-                                             L.total - L.ws, s.stream);
+        ssort_status rc = ce == hipSuccess ? ssort_sort_batched(s.ctx, &flat, (const uint32_t *)(dev + L.setb), L.m,
+                                                                (uint32_t *)(dev + L.perm), (uint32_t *)(dev + L.lcp),
+                                                                dev + L.ws, L.total - L.ws, s.stream)
+                                           : SSORT_EDEVICE;
         if (ce == hipSuccess) ce = hipMemcpyAsync(s.stage_out, dev + L.perm, L.out_bytes, hipMemcpyDeviceToHost, s.stream);
         if (ce == hipSuccess) ce = hipEventRecord(s.done, s.stream);
         if (ce != hipSuccess && rc == SSORT_OK) rc = SSORT_EDEVICE;
@@ -164,12 +260,15 @@ struct ssort_server {
         ssort_status dev_rc = ssort_query_error(s.ctx, s.stream);
         const uint32_t *perm = s.stage_out;
         const uint32_t *lcp = (const uint32_t *)((const uint8_t *)s.stage_out + (L.lcp - L.perm));
-        const auto now = clk::now();
-        for (uint32_t k = 0; k < s.jobs.size(); ++k) {
-            JobRec &r = jobs[s.jobs[k]];
+        pool->run(s.jobs.size(), [&](size_t k) {
+            const JobRec &r = jobs.at(s.jobs[k]);
             const uint32_t b = s.set_begin[k], n = r.job.n;
             if (r.job.out_perm) memcpy(r.job.out_perm, perm + b, 4ull * n);
             if (r.job.out_lcp) memcpy(r.job.out_lcp, lcp + b, 4ull * n);
+        });
+        const auto now = clk::now();
+        for (uint32_t k = 0; k < s.jobs.size(); ++k) {
+            JobRec &r = jobs[s.jobs[k]];
             if (r.status == SSORT_OK) r.status = dev_rc;
             r.state = 2;
             r.t_done = now;
@@ -251,6 +350,7 @@ ssort_status ssort_server_create(int device, size_t hbm_budget, uint32_t slots, 
         return SSORT_ENOMEM;
     }
     S->adm = new ssd::Admission(hbm_budget, 256);
+    S->pool = new CopyPool(7);
     S->slots.resize(slots);
     for (auto &s : S->slots) {
         if (ssort_create(device, t, &s.ctx) != SSORT_OK || hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -342,6 +442,7 @@ void ssort_server_destroy(ssort_server *S) {
     }
     if (S->arena) (void)hipFree(S->arena);
     delete S->adm;
+    delete S->pool;
     delete S;
 }
 
