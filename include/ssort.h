@@ -78,7 +78,11 @@ typedef struct {
  *  base_threshold  segments of at most this many strings go to the LCP-aware
  *                  base case (64..1024).
  *  flags           SSORT_VALIDATE: check strings for bounds and zero bytes
- *                  first (one extra pass over the characters). */
+ *                  first (one extra pass over the characters);
+ *                  SSORT_EQUAL: classify with an equality test at every tree
+ *                  node and an early exit ("S5-Equal", fourth equality-check
+ *                  variant of the implementation details of S5) instead of a
+ *                  full descent and one equality test ("S5-Unroll"). */
 typedef struct {
     uint32_t v;
     uint32_t keys_per_thread;
@@ -87,6 +91,7 @@ typedef struct {
 } ssort_tuning;
 
 #define SSORT_VALIDATE 1u
+#define SSORT_EQUAL 2u
 
 typedef struct ssort_ctx ssort_ctx;
 

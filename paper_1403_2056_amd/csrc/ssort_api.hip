@@ -78,6 +78,7 @@ bool valid_tuning(const ssort_tuning &t) {
     if (v < 1 || v > VMAX || ((v + 1) & v) != 0) return false;
     if (t.keys_per_thread != 4 && t.keys_per_thread != 8) return false;
     if (t.base_threshold < 16 || t.base_threshold > (uint32_t)CH) return false;
+    if (t.flags & ~(SSORT_VALIDATE | SSORT_EQUAL)) return false;
     return true;
 }
 
@@ -162,6 +163,7 @@ Params make_params(const ssort_ctx *c, const ssort_strings *in, uint32_t *perm, 
     P.ntiles = L.ntiles;
     P.tbase = c->tun.base_threshold;
     P.vmax = c->tun.v;
+    P.equal = (c->tun.flags & SSORT_EQUAL) ? 1u : 0u;
     P.limit_ticks = (unsigned long long)c->wait_ms * c->wall_khz;
     P.limit_iters = (unsigned long long)c->wait_ms * 2000ull;   // polls take well over 0.5 us each
     return P;

@@ -149,7 +149,10 @@ struct Split {
     uint64_t tree[VMAX + 1];   // level order, tree[1..v]
     uint8_t hl[VMAX + 1];      // hl[l] = lcp(x[l-1], x[l]) in bytes, hl[0] = hl[v] = 0
     uint8_t zr[VMAX + 1];      // zr[l] = x[l] ends its string (last byte zero)
-    uint32_t v, d, nb, nbits, ndistinct, pad[3];
+    uint32_t v, d, nb, nbits, ndistinct;
+    uint32_t ulast;            // ranks >= ulast repeat x[ulast] (tree padded with the largest key)
+    uint32_t equal;            // classify with an equality test at every node (S5-Equal)
+    uint32_t pad;
 };
 
 // Level-order node of the splitter with in-order rank r in a perfect tree of
@@ -175,6 +178,29 @@ __device__ __forceinline__ uint32_t classify(uint64_t c, const Split &sp) {
     return 2 * l + ((l < sp.v && splitter(sp, l) == c) ? 1u : 0u);
 }
 
+// S5-Equal (fourth variant of the implementation details): test equality at
+// every node and stop at the first equal splitter; its in-order rank r gives
+// the equality bucket 2r+1 (the first copy when the tree is padded, so the
+// bucket is the same as above).  Without a match the descent ends at a leaf.
+__device__ __forceinline__ uint32_t classify_equal(uint64_t c, const Split &sp) {
+    uint32_t i = 1;
+    for (uint32_t l = 0; l < sp.d; ++l) {
+        const uint64_t t = sp.tree[i];
+        if (c == t) {
+            const uint32_t delta = 31 - __clz(i);
+            const uint32_t p = i - (1u << delta);
+            const uint32_t r = ((2 * p + 1) << (sp.d - 1 - delta)) - 1;
+            return 2 * min(r, sp.ulast) + 1;
+        }
+        i = 2 * i + (c > t ? 1u : 0u);
+    }
+    return 2 * (i - (sp.v + 1));
+}
+
+__device__ __forceinline__ uint32_t classify_any(uint64_t c, const Split &sp) {
+    return sp.equal ? classify_equal(c, sp) : classify(c, sp);
+}
+
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
     x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
     return x;
@@ -191,7 +217,8 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 // flags.  `samp`, `srt` need SAMPLE_MAX+1 entries, `fl` SAMPLE_MAX+1, tmp NW.
 template <typename Load>
 __device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
-                                 uint64_t *samp, uint64_t *srt, uint32_t *fl, uint32_t *tmp, Load load) {
+                                                 uint32_t equal, uint64_t *samp, uint64_t *srt, uint32_t *fl,
+                                                 uint32_t *tmp, Load load) {
     const int tid = threadIdx.x;
     const uint32_t a = size < (uint32_t)(2 * (vmax + 1) - 1) ? size : (uint32_t)(2 * (vmax + 1) - 1);
     const bool all = size <= a;
@@ -242,6 +269,8 @@ __device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint3
         while ((1u << nbits) < 2 * v + 2) ++nbits;
         sp.nbits = nbits;
         sp.ndistinct = U;
+        sp.ulast = U <= vmax ? U - 1 : v;
+        sp.equal = equal;
     }
     __syncthreads();
     for (uint32_t j = 1 + tid; j <= v; j += NT) {

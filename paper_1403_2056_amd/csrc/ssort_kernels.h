@@ -51,6 +51,7 @@ struct Params {
     uint32_t ntiles;
     uint32_t tbase;
     uint32_t vmax;
+    uint32_t equal;          // S5-Equal classification
     unsigned long long limit_ticks;
     unsigned long long limit_iters;
     uint32_t dbg;            // debug step: stop after the root redistribution

@@ -450,7 +450,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
         const Rec r = load_rec(P, meta, begin + e);
         return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
     };
-    select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, L.u.s.samp,
+    select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, P.equal, L.u.s.samp,
                      L.u.s.srt, L.u.s.fl, L.tmp, kload);
     mark(L, PH_SAMPLE);
     if (uni(L.sp.ndistinct) == 1 && (splitter(L.sp, 0) & 0xFF) != 0) {
@@ -506,7 +506,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
         __syncthreads();
         h = uni(L.ext_min);
         mark(L, PH_EXTEND);
-        select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, L.u.s.samp,
+        select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, P.equal, L.u.s.samp,
                          L.u.s.srt, L.u.s.fl, L.tmp, kload);
         mark(L, PH_SAMPLE);
     }
@@ -538,7 +538,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
             const bool valid = e < S;
-            const uint32_t m = valid ? classify(k[j], L.sp) : nb;
+            const uint32_t m = valid ? classify_any(k[j], L.sp) : nb;
             const uint64_t mask = match_any(m, nbits);
             if (valid && lane == 63 - (int)__clzll(mask)) atomicAdd(&L.hist[m], (uint32_t)__popcll(mask));
             if (valid) P.bkt[begin + e] = (uint16_t)m;
@@ -825,7 +825,7 @@ __global__ __launch_bounds__(NT) void k_root_sample(Params P, uint32_t depth) {
         const Rec r = make_rec(P.S, e);
         return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
     };
-    select_splitters(L.sp, P.S.n, depth, 0x2545F491u ^ P.S.n, P.vmax, L.samp, L.srt, L.fl, L.tmp, kload);
+    select_splitters(L.sp, P.S.n, depth, 0x2545F491u ^ P.S.n, P.vmax, P.equal, L.samp, L.srt, L.fl, L.tmp, kload);
     const uint32_t *src = (const uint32_t *)&L.sp;
     uint32_t *dst = (uint32_t *)P.gsplit;
     for (uint32_t i = threadIdx.x; i < sizeof(Split) / 4; i += NT) dst[i] = src[i];
@@ -869,7 +869,7 @@ __global__ __launch_bounds__(NT) void k_root_classify(Params P, uint32_t depth) 
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
             const bool valid = e < n;
-            const uint32_t m = valid ? classify(k[j], sp) : nb;
+            const uint32_t m = valid ? classify_any(k[j], sp) : nb;
             const uint64_t mask = match_any(m, nbits);
             if (valid && lane == 63 - (int)__clzll(mask)) atomicAdd(&hist[m], (uint32_t)__popcll(mask));
             if (valid) P.bkt[e] = (uint16_t)m;

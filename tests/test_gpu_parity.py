@@ -146,6 +146,23 @@ def test_tunings_give_identical_results(v, k, tb):
     assert_parity(s, W.suffixes(1 << 16, seed=13), f"tuning v={v} k={k} tb={tb} suffixes")
 
 
+@pytest.mark.parametrize("v", [7, 255])
+def test_equal_classification_variant(v):
+    """S5-Equal (equality test at every node, early exit) gives the same
+    buckets as the lower-bound definition and the same sorted output."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_2056_amd import ssort
+    s = ssort.Sorter(0, v=v, flags=ssort.SSORT_EQUAL)
+    s.set_wait_limit(10000)
+    for ss, label in ((W.plain(90000, seed=40), "plain"), (W.prefixes(1 << 17, seed=41, n_prefix=32), "prefixes"),
+                      (W.from_list([b"dup"] * 3000 + [b"a", b"zz"]), "few keys")):
+        out = s.debug_step(ssort.strings_to_device(ss), 0)
+        keys = oracle.keys(ss, np.arange(ss.n), 0)
+        assert np.array_equal(out["bucket"].astype(np.uint32), oracle.classify(keys, out["split"])), label
+        assert_parity(s, ss, f"S5-Equal v={v} {label}")
+
+
 def test_validate_reports_zero_byte():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
