@@ -26,6 +26,14 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "worker_traffic_prefixes_n16M.json")
 
 
+WORKLOAD_TEXT = {
+    "prefixes": "long shared prefixes: n=2^{n} strings, 4096 strings per random prefix (len 10-60) + "
+                "random suffix (len 5-80), 64-symbol alphabet, 20% exact duplicates, CSR u64 offsets",
+    "suffixes": "suffix sort: all 2^{n} suffixes of a DNA text of copied, 1%-mutated 2 KiB blocks (strings run to the text's end)",
+    "plain": "2^{n} strings of uniform length 8-32 over a-z, 5% duplicates",
+}
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1403_2056_amd", "csrc")
@@ -217,6 +225,8 @@ def main():
     ap.add_argument("--v", type=int, default=255)
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--tb", type=int, default=128)
+    ap.add_argument("--equal", action="store_true", help="S5-Equal classification")
+    ap.add_argument("--workload", default="prefixes", help="plain mode: prefixes, suffixes or plain")
     ap.add_argument("--mode", choices=["plain", "batched", "serve"], default="plain")
     ap.add_argument("--sets", type=int, default=4096)
     ap.add_argument("--retune", action="store_true")
@@ -237,10 +247,11 @@ def main():
 
     n = 1 << args.n_log2
     t0 = time.time()
-    ss = workloads.prefixes(n) if n == 1 << 24 else workloads.by_name("prefixes", n)
+    ss = workloads.by_name(args.workload, n)
     print(f"[bench] generated n={ss.n} N={len(ss.chars)} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     d = ssort.strings_to_device(ss)
-    sorter = ssort.Sorter(0, v=args.v, keys_per_thread=args.k, base_threshold=args.tb)
+    sorter = ssort.Sorter(0, v=args.v, keys_per_thread=args.k, base_threshold=args.tb,
+                          flags=ssort.SSORT_EQUAL if args.equal else 0)
     sorter.profile(True)
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     lcp = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -296,7 +307,8 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tf = json.load(open(TRAFFIC_FILE))
-        if tf.get("source_hash") == source_hash():
+        if (tf.get("source_hash") == source_hash() and args.workload == "prefixes" and n == 1 << 24
+                and sorter.tuning.as_dict() == tf.get("tuning", sorter.tuning.as_dict())):
             traffic = tf.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
@@ -328,8 +340,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": "long shared prefixes: n=2^24 strings, 4096 random prefixes (len 10-60) + "
-                               "random suffix (len 5-80), 64-symbol alphabet, 20% exact duplicates, CSR u64 offsets",
+        "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload).format(n=args.n_log2),
                    "n": n, "N": N, "D": D, "D_over_N": round(D / N, 4),
                    "tuning": sorter.tuning.as_dict()},
         "d_gbps": round(D / t_s / 1e9, 3),

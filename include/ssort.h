@@ -99,17 +99,30 @@ typedef struct ssort_ctx ssort_ctx;
  *  segments     classification steps run (one per segment of > base_threshold strings)
  *  strings      sum over those steps of their sizes (the active strings per level)
  *  base_groups  groups handled by the base case
- *  max_depth    largest depth (bytes) at which a step or base-case round ran */
+ *  max_depth    largest depth (bytes) at which a step or base-case round ran
+ *  base_chunks  base-case chunks (one workgroup each, several groups)
+ *  base_rounds  base-case rounds summed over chunks */
 typedef struct {
     uint64_t segments;
     uint64_t strings;
     uint64_t base_groups;
     uint64_t max_depth;
     /* persistent-worker time per phase, summed over workgroups, in wall-clock
-     * ticks (ssort_device_info out[2] kHz): 0 waiting for work, 1 sample and
+     * ticks (ssort_device_info out[2] kHz): 0 waiting for a task, 1 sample and
      * tree, 2 classify and count, 3 redistribution, 4 child scheduling and
-     * identical buckets, 5 base case, 6 common-prefix extension, 7 other */
-    uint64_t phase_ticks[8];
+     * identical buckets, 5 base case (loading and writing the chunk),
+     * 6 common-prefix extension of a segment, 7 other, 8 base-case prefix
+     * extension, 9 base-case key gathers, 10 base-case ranking and class
+     * splitting, 11 the last wait (for the queue to drain), 12-15 unused */
+    uint64_t phase_ticks[16];
+    uint64_t base_chunks;
+    uint64_t base_rounds;
+    /* slowest work-queue task: wall-clock ticks << 24 | its string count
+     * (capped at 2^24 - 1); slowest base-case chunk: ticks << 24 | rounds
+     * << 12 | strings */
+    uint64_t max_task;
+    uint64_t max_chunk;
+    uint64_t published_chunks;   /* base-case chunks handed to other workgroups */
 } ssort_stats_t;
 
 /* Create a context on HIP device `device` (the current device if < 0).

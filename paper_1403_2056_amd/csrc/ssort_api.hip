@@ -37,7 +37,7 @@ uint64_t next_pow2(uint64_t x) {
 }
 
 struct Layout {
-    size_t ctl, r0, r1, bkt, ring, split, hist, totals, total;
+    size_t ctl, r0, r1, bkt, ring, split, hist, totals, desc, total;
     uint64_t cap;
     uint32_t ntiles;
 };
@@ -47,10 +47,13 @@ Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     const uint32_t K = c->tun.keys_per_thread;
     const uint64_t tile = (uint64_t)NT * K * ROOT_CHUNKS;
     L.ntiles = n ? (uint32_t)((n + tile - 1) / tile) : 0u;
-    // queued tasks are disjoint segments of more than base_threshold strings
-    // plus the root tasks; twice that bound leaves every slot's previous
-    // occupant consumed long before the slot is reused
-    const uint64_t live = (uint64_t)n / (c->tun.base_threshold + 1) + m + NBMAX + (uint64_t)c->worker_blocks;
+    // queued tasks are segments of more than base_threshold strings (at most
+    // two per such disjoint set of strings), the root tasks and published
+    // base-case chunks of at least (chunk - threshold) / 2 >= 128 strings;
+    // twice that bound leaves every slot's previous occupant consumed long
+    // before the slot is reused
+    const uint64_t live = 2 * (uint64_t)n / (c->tun.base_threshold + 1) + (uint64_t)n / 128 + m + NBMAX +
+                          (uint64_t)c->worker_blocks;
     L.cap = next_pow2(2 * live + 1024);
     size_t off = 0;
     L.ctl = off;
@@ -69,6 +72,8 @@ Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     off = align_up(off + 4 * (size_t)NBPAD * L.ntiles, 256);
     L.totals = off;
     off = align_up(off + 4 * (size_t)NBPAD, 256);
+    L.desc = off;   // at most one descriptor per base-case group
+    off = align_up(off + sizeof(GroupDesc) * (size_t)n, 256);
     L.total = off;
     return L;
 }
@@ -158,6 +163,8 @@ Params make_params(const ssort_ctx *c, const ssort_strings *in, uint32_t *perm, 
     P.gsplit = (Split *)(w + L.split);
     P.hist = (uint32_t *)(w + L.hist);
     P.totals = (uint32_t *)(w + L.totals);
+    P.desc = (GroupDesc *)(w + L.desc);
+    P.desc_cap = in->n;
     P.set_begin = set_begin;
     P.m = m;
     P.ntiles = L.ntiles;
@@ -353,11 +360,16 @@ ssort_status ssort_stats(ssort_ctx *ctx, ssort_stats_t *out, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(&c, ctx->last_ws, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess) return SSORT_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return SSORT_EDEVICE;
-    out->segments = c.st_segments;
-    out->strings = c.st_strings;
-    out->base_groups = c.st_base;
-    out->max_depth = c.st_maxdepth;
-    for (int k = 0; k < 8; ++k) out->phase_ticks[k] = c.ph[k];
+    out->segments = c.st[ST_SEGMENTS];
+    out->strings = c.st[ST_STRINGS];
+    out->base_groups = c.st[ST_BASE];
+    out->max_depth = c.st[ST_MAX_DEPTH];
+    for (int k = 0; k < NPH; ++k) out->phase_ticks[k] = c.ph[k];
+    out->base_chunks = c.st[ST_CHUNKS];
+    out->base_rounds = c.st[ST_ROUNDS];
+    out->max_task = c.st[ST_MAX_TASK];
+    out->max_chunk = c.st[ST_MAX_CHUNK];
+    out->published_chunks = c.st[ST_PUBCHUNKS];
     return SSORT_OK;
 }
 

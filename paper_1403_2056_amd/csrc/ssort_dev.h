@@ -70,7 +70,49 @@ __device__ __forceinline__ uint64_t key_at(const uint8_t *chars, uint64_t nchars
     return k;
 }
 
+// The 32 characters of a string from depth h as four keys (key_at at h,
+// h + 8, h + 16, h + 24), from the at most five aligned words that hold them.
+__device__ __forceinline__ void keys32_at(const uint8_t *chars, uint64_t nchars, uint64_t st, uint32_t ln, uint32_t h,
+                                          uint64_t k[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = 0;
+    if (h >= ln) return;
+    const uint64_t p = st + h;
+    if (p >= nchars) return;
+    const uint32_t rem = (uint32_t)min((uint64_t)(ln - h), nchars - p);
+    const uintptr_t a = (uintptr_t)(chars + p);
+    const uintptr_t a0 = a & ~(uintptr_t)7;
+    const uint32_t sh = (uint32_t)(a & 7);
+    const uint32_t nw = (sh + min(rem, 32u) + 7) >> 3;   // words holding wanted bytes, 1..5
+    uint64_t w[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) w[i] = (uint32_t)i < nw ? *(const uint64_t *)(a0 + 8 * i) : 0ull;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint64_t lo = sh ? (w[j] >> (8 * sh)) | (w[j + 1] << (64 - 8 * sh)) : w[j];
+        uint64_t kj = __builtin_bswap64(lo);
+        const int r = (int)rem - 8 * j;
+        if (r <= 0) kj = 0;
+        else if (r < 8) kj &= ~0ull << (8 * (8 - r));
+        k[j] = kj;
+    }
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// threadIdx.x behind an empty asm statement, so that the optimiser cannot
+// hoist what is derived from it (per-thread LDS addresses) out of the phase
+// that uses it: hoisted to the start of the persistent kernel, dozens of
+// such addresses stay live across its whole loop and push other values into
+// scratch.  Every phase of the worker takes its thread index from here.
+#ifndef SSD_OPAQUE
+#define SSD_OPAQUE(x) asm volatile("" : "+v"(x))
+#endif
+__device__ __forceinline__ int tid_here() {
+    int t = (int)threadIdx.x;
+    SSD_OPAQUE(t);
+    return t;
+}
 
 // Broadcast a value that is equal in every thread (read from LDS after a
 // barrier) so that the compiler treats it as uniform.  Every branch or loop
@@ -117,7 +159,7 @@ struct MaxOp { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { re
 // Returns the total.  Must be called by all threads; includes barriers.
 template <typename Op>
 __device__ __forceinline__ uint32_t block_scan(uint32_t *a, int len, uint32_t *tmp, bool exclusive, Op op, uint32_t ident) {
-    const int tid = threadIdx.x;
+    const int tid = tid_here();
     const int per = (len + NT - 1) / NT;
     const int lo = tid * per;
     const int hi = min(len, lo + per);
@@ -219,7 +261,7 @@ template <typename Load>
 __device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
                                                  uint32_t equal, uint64_t *samp, uint64_t *srt, uint32_t *fl,
                                                  uint32_t *tmp, Load load) {
-    const int tid = threadIdx.x;
+    const int tid = tid_here();
     const uint32_t a = size < (uint32_t)(2 * (vmax + 1) - 1) ? size : (uint32_t)(2 * (vmax + 1) - 1);
     const bool all = size <= a;
     const uint32_t stride = all ? 1u : size / a;

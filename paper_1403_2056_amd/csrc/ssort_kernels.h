@@ -4,19 +4,36 @@
 
 namespace ssd {
 
-// Control block at the start of the workspace.
+constexpr int NPH = 16;
+constexpr int NST = 9;
+
+// Control block at the start of the workspace.  The queue counters each
+// sit on a cache line of their own: every idle workgroup polls `pending`,
+// and traffic to one line is served by one L2 channel, whose congestion
+// slows every other access mapped to that channel.  Statistics are summed
+// per workgroup in LDS and added here once, when the workgroup exits.
 struct Ctl {
-    unsigned long long head;      // next queue position to claim
-    unsigned long long tail;      // next queue position to fill
-    unsigned long long pending;   // tasks enqueued or running, not finished
-    unsigned long long error;     // bit mask of device errors
-    unsigned long long st_segments, st_strings, st_base, st_maxdepth;
-    unsigned long long ph[8];     // worker time per phase, wall-clock ticks summed over workgroups
+    alignas(128) unsigned long long head;      // next queue position to claim
+    alignas(128) unsigned long long tail;      // next queue position to fill
+    alignas(128) unsigned long long pending;   // tasks enqueued or running, not finished
+    alignas(128) unsigned long long error;     // bit mask of device errors
+    alignas(128) unsigned long long desc_top;  // group descriptors handed out
+    alignas(128) unsigned long long st[NST];   // statistics (ST_*)
+    unsigned long long ph[NPH];                // worker time per phase, wall-clock ticks summed over workgroups
+};
+
+// statistics: sums, except the ST_MAX_* entries (maxima)
+enum {
+    ST_SEGMENTS = 0, ST_STRINGS = 1, ST_BASE = 2, ST_CHUNKS = 3, ST_ROUNDS = 4, ST_PUBCHUNKS = 5,
+    ST_MAX_DEPTH = 6,   // largest classification depth
+    ST_MAX_TASK = 7,    // longest task: ticks << 24 | size (capped)
+    ST_MAX_CHUNK = 8,   // longest base chunk: ticks << 24 | rounds << 12 | strings
 };
 
 // worker phases timed on the device
 enum { PH_WAIT = 0, PH_SAMPLE = 1, PH_CLASSIFY = 2, PH_SCATTER = 3, PH_CHILDREN = 4, PH_BASE = 5,
-       PH_EXTEND = 6, PH_OTHER = 7 };
+       PH_EXTEND = 6, PH_OTHER = 7, PH_BEXT = 8, PH_BKEY = 9, PH_BRANK = 10,
+       PH_DRAIN = 11 };
 
 enum : unsigned long long { ERR_TIMEOUT = 1, ERR_BOUNDS = 2, ERR_ZERO = 4, ERR_QUEUE = 8, ERR_INTERNAL = 16 };
 
@@ -25,6 +42,12 @@ enum : uint32_t {
     M_PARITY = 1u,       // records of the segment are in R[1] (else R[0])
     M_IDENT_SRC = 2u,    // records come straight from the input (identity order)
     M_IDENT = 4u,        // all strings identical (equality bucket of a terminated splitter)
+    M_CHUNK = 8u,        // a base-case chunk: begin = first group descriptor, size = groups, depth = strings
+};
+
+// A base-case group: global start, size and common depth of its strings.
+struct __align__(16) GroupDesc {
+    uint32_t start, size, depth, pad;
 };
 
 // One queue slot (bounded MPMC ring with per-slot sequence numbers).
@@ -46,6 +69,8 @@ struct Params {
     Split *gsplit;           // root step splitters (global copy)
     uint32_t *hist;          // root step tile histograms, bucket-major [nb][ntiles]
     uint32_t *totals;        // root step bucket totals [NBPAD]
+    GroupDesc *desc;         // base-case group descriptors (at most one per group)
+    uint64_t desc_cap;
     const uint32_t *set_begin;   // batched: m+1 set boundaries, else null
     uint32_t m;              // number of sets (1 for a plain sort)
     uint32_t ntiles;

@@ -34,11 +34,26 @@ __device__ __forceinline__ bool out_is_r1(uint32_t meta) {
 __device__ __forceinline__ unsigned long long ld_rlx(unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_rel(unsigned long long *p, unsigned long long v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_rlx(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// queue counters carry no data: relaxed
 __device__ __forceinline__ unsigned long long add_agent(unsigned long long *p, unsigned long long v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Make the workgroup's global writes visible to every workgroup of the
+// device.  The L2 caches of the chip's dies are not coherent with each other
+// for this memory, so an agent-scope release writes the die's L2 back; that
+// is costly, so each wave first waits until its own stores have reached the
+// L2 and then a single wave releases (instead of every wave).  Whatever is
+// stored after this (queue slot sequence numbers) can be relaxed: a reader
+// that sees it and then acquires sees the data.
+__device__ __forceinline__ void release_wg() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -64,7 +79,7 @@ template <int K>
 __device__ __forceinline__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, const uint32_t (&m)[K],
                               const Rec (&r)[K], uint32_t cnt, uint32_t *run, Rec *out, uint32_t nlim,
                               unsigned long long *err) {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tid = tid_here(), w = tid >> 6, lane = tid & 63;
     const uint32_t nb = uni(sp.nb);
     const int nbits = (int)uni(sp.nbits);
     uint32_t *wc = (uint32_t *)&L.wcnt[0][0];
@@ -129,11 +144,8 @@ __device__ __forceinline__ uint32_t lcp_from(const Params &P, uint64_t sta, uint
     for (;;) {
         if (l >= *stop) return l;
         uint64_t ka[4], kb[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ka[i] = key_at(P.S.chars, P.S.nchars, sta, lna, l + 8 * i);
-            kb[i] = key_at(P.S.chars, P.S.nchars, stb, lnb, l + 8 * i);
-        }
+        keys32_at(P.S.chars, P.S.nchars, sta, lna, l, ka);
+        keys32_at(P.S.chars, P.S.nchars, stb, lnb, l, kb);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             if (ka[i] != kb[i]) return l + 8 * i + (uint32_t)(__clzll(ka[i] ^ kb[i]) >> 3);
@@ -143,35 +155,94 @@ __device__ __forceinline__ uint32_t lcp_from(const Params &P, uint64_t sta, uint
     }
 }
 
+// Lanes per comparison for n pending long comparisons: the whole wave (512
+// bytes a trip) for a few, halving down to 8 lanes (64 bytes a trip); 0 when
+// there are more than a workgroup's lanes can cover 8 at a time (then every
+// thread compares its own pairs).
+__device__ __forceinline__ uint32_t group_width(uint32_t n) {
+    if (n > (uint32_t)NT / 8) return 0;
+    uint32_t g = 64;
+    while (g > 8 && n * g > (uint32_t)NT) g >>= 1;
+    return g;
+}
+
+// Length of the common prefix of strings a and b, known to agree on [0, from),
+// computed by a group of G consecutive lanes (G a power of two, 8..64; the
+// group's lanes pass the same arguments): lane j compares the 8 bytes at
+// l + 8j, one ballot finds the first lane that sees a difference or the end,
+// so one trip covers 8G bytes.  A lane whose position is at or beyond *stop
+// (read by each lane; the caller only needs values below it, and *stop only
+// decreases) ends the comparison there and the result is that position,
+// which every earlier lane has verified to be a common prefix.  Called by all
+// 64 lanes of the wave together (groups with on == false take part without a
+// pair); the wave loops until its last group is done.
+__device__ __forceinline__ uint32_t group_lcp(const Params &P, uint32_t G, bool on, uint64_t sta, uint32_t lna,
+                                              uint64_t stb, uint32_t lnb, uint32_t from, const volatile uint32_t *stop) {
+    const uint32_t lane = lane_id();
+    const uint32_t gl = lane & (G - 1), gb = lane & ~(G - 1);
+    const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << G) - 1) << gb;
+    uint32_t res = 0;
+    bool live = on;
+    for (uint32_t l = from; __ballot(live) != 0; l += 8 * G) {
+        bool f = false;
+        uint32_t v = 0;
+        if (live) {
+            const uint32_t pos = l + 8 * gl;
+            const bool cut = pos >= *stop;
+            uint64_t ka = 0, kb = 0;
+            if (!cut) {
+                ka = key_at(P.S.chars, P.S.nchars, sta, lna, pos);
+                kb = key_at(P.S.chars, P.S.nchars, stb, lnb, pos);
+            }
+            f = cut || ka != kb || (ka & 0xFF) == 0;
+            v = cut ? pos : (ka != kb ? pos + (uint32_t)(__clzll(ka ^ kb) >> 3) : min(lna, lnb));
+        }
+        const uint64_t m = __ballot(f) & gmask;
+        const uint32_t got = __shfl(v, m ? (int)__builtin_ctzll(m) : (int)lane, 64);
+        if (live && m) {
+            res = got;
+            live = false;
+        }
+    }
+    return res;
+}
+
 // ---------------------------------------------------------------------------
 // LCP-aware base case (semantics of LCP insertion sort, Algorithm 5: sorted
 // order, stable by input index, and the adjacent LCPs).  A chunk of up to C
 // strings from several groups; each group is sorted independently from its
-// common depth.  Rounds: gather the 8-byte key at the class depth, rank every
-// element inside its class by (key, index), then split classes at key
-// changes; adjacent elements whose keys differ get lcp = depth + equal leading
-// bytes, equal keys ending their strings are identical strings (lcp = length),
-// equal keys without an end go on at depth + 8.
+// common depth.  Elements live at positions; a class is a run of positions
+// [start, end) whose strings agree up to the class depth.  Rounds: gather the
+// 8-byte key at the class depth, rank every element inside its class by
+// (key, position) — positions inside a class follow input order, because
+// every redistribution before the base case and every round is stable — and
+// split classes at key changes: an element that starts a run of equal keys
+// gets lcp = depth + equal leading bytes with the largest smaller key of its
+// class, equal keys ending their strings are identical strings (lcp =
+// length), runs of at least two equal keys without an end stay active at
+// depth + 8.  An element whose depth is DONE needs no more rounds.
+constexpr uint32_t DONE = 0xFFFFFFFFu;
+
 template <int C>
 struct BaseLDS {
     uint64_t st[C];
-    uint64_t key[C];
+    uint64_t kq[C];          // keys by position (also the extension's pair list)
     uint32_t ln[C];
     uint32_t id[C];
-    uint32_t d[C];
+    uint32_t d[C];           // per element: class depth, or DONE
     uint32_t scr[C];
-    uint16_t cst[C];
-    uint16_t ord[2][C];
-    uint8_t act[C];
+    uint32_t cls[C];         // per position: class start | class end << 16
+    uint16_t ord[2][C];      // element at each position
     uint32_t any;
+    uint32_t nlist;
 };
 
 // Group accessor: group g of the chunk has global start gstart(g), size
 // gsize(g), common depth gdepth(g) and chunk-local exclusive prefix gpre(g).
-template <int C, typename G>
+template <int C, typename G, typename Mark>
 __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const Rec *src, uint32_t setbase,
-                           uint32_t ng, uint32_t M, const G &grp) {
-    const int tid = threadIdx.x;
+                           uint32_t ng, uint32_t M, const G &grp, Mark mk, unsigned long long *st) {
+    const int tid = tid_here();
     auto find = [&](uint32_t q) -> uint32_t {
         uint32_t lo = 0, hi = ng;           // largest g with gpre(g) <= q
         while (hi - lo > 1) {
@@ -185,6 +256,7 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
         return grp.gstart(g) + (q - grp.gpre(g));
     };
     constexpr int PER = (C + NT - 1) / NT;   // positions per thread
+    const unsigned long long t_start = wall_clock64();
     {
         uint32_t gg[PER];
         Rec rr[PER];
@@ -201,114 +273,178 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
             const uint32_t q = tid + u * NT;
             if (q >= M) continue;
             const uint32_t g = gg[u];
+            const uint32_t c0 = grp.gpre(g), sz = grp.gsize(g);
             B.st[q] = rr[u].st;
             B.ln[q] = rr[u].ln;
             B.id[q] = rr[u].id;
-            B.d[q] = grp.gdepth(g);
-            B.cst[q] = (uint16_t)grp.gpre(g);
+            B.d[q] = sz >= 2 ? grp.gdepth(g) : DONE;
+            B.cls[q] = c0 | ((c0 + sz) << 16);
             B.ord[0][q] = (uint16_t)q;
-            B.act[q] = grp.gsize(g) >= 2 ? 1 : 0;
         }
     }
     if (tid == 0) B.any = 0;
     __syncthreads();
+    mk(PH_BASE);
     int cur = 0;
+    uint32_t rounds = 0;
     bool more = true, first = true;
     while (more) {
+        ++rounds;
         // after the first round every active class holds equal keys: it first
         // jumps to its exact common prefix, each member compared with the
         // class's first member from the class depth on (instead of one round
         // per 8 equal bytes)
         if (!first) {
         for (uint32_t q = tid; q < M; q += NT)
-            if (B.act[q] && q == B.cst[q]) B.scr[q] = 0xFFFFFFFFu;
+            if (q == (B.cls[q] & 0xFFFF) && B.d[B.ord[cur][q]] != DONE) B.scr[q] = 0xFFFFFFFFu;
+        if (tid == 0) B.nlist = 0;
         __syncthreads();
-        for (uint32_t q = tid; q < M; q += NT)
-            if (B.act[q] && q != B.cst[q]) {
-                const uint32_t c0 = B.cst[q];
-                const uint32_t e = B.ord[cur][q], f = B.ord[cur][c0];
-                const uint32_t l = lcp_from(P, B.st[f], B.ln[f], B.st[e], B.ln[e], B.d[e], &B.scr[c0]);
-                atomicMin(&B.scr[c0], l);
+        // first 32 bytes of every member against its class head; the pairs
+        // still equal go to a list (kept where the keys go: they are gathered
+        // again after the extension)
+        uint32_t *list = reinterpret_cast<uint32_t *>(B.kq);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t q = tid + u * NT;
+            if (q >= M) continue;
+            const uint32_t c0 = B.cls[q] & 0xFFFF, e = B.ord[cur][q];
+            if (q == c0 || B.d[e] == DONE) continue;
+            const uint32_t f = B.ord[cur][c0], de = B.d[e];
+            uint64_t ka[4], kb[4];
+            keys32_at(P.S.chars, P.S.nchars, B.st[f], B.ln[f], de, ka);
+            keys32_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], de, kb);
+            uint32_t l = 0xFFFFFFFFu;
+#pragma unroll
+            for (int i = 3; i >= 0; --i) {
+                if (ka[i] != kb[i]) l = de + 8 * i + (uint32_t)(__clzll(ka[i] ^ kb[i]) >> 3);
+                else if ((ka[i] & 0xFF) == 0) l = min(B.ln[f], B.ln[e]);
             }
+            if (l != 0xFFFFFFFFu) atomicMin(&B.scr[c0], l);
+            else list[atomicAdd(&B.nlist, 1u)] = q;
+        }
         __syncthreads();
-        for (uint32_t q = tid; q < M; q += NT)
-            if (B.act[q]) B.d[B.ord[cur][q]] = B.scr[B.cst[q]];
+        // the rest: by groups of lanes when few, by single threads when many
+        {
+            const uint32_t n = uni(B.nlist);
+            const uint32_t gw = group_width(n);
+            if (gw) {
+                for (uint32_t i0 = 0; i0 < n; i0 += NT / gw) {
+                    const uint32_t i = i0 + tid / gw;
+                    const bool on = i < n;
+                    const uint32_t q = on ? list[i] : 0u, c0 = B.cls[q] & 0xFFFF;
+                    const uint32_t e = B.ord[cur][q], f = B.ord[cur][c0];
+                    const uint32_t l = group_lcp(P, gw, on, B.st[f], B.ln[f], B.st[e], B.ln[e], B.d[e] + 32, &B.scr[c0]);
+                    if (on && (tid & (gw - 1)) == 0) atomicMin(&B.scr[c0], l);
+                }
+            } else {
+                for (uint32_t i = tid; i < n; i += NT) {
+                    const uint32_t q = list[i], c0 = B.cls[q] & 0xFFFF;
+                    const uint32_t e = B.ord[cur][q], f = B.ord[cur][c0];
+                    const uint32_t l = lcp_from(P, B.st[f], B.ln[f], B.st[e], B.ln[e], B.d[e] + 32, &B.scr[c0]);
+                    atomicMin(&B.scr[c0], l);
+                }
+            }
+        }
         __syncthreads();
+        for (uint32_t q = tid; q < M; q += NT) {
+            const uint32_t e = B.ord[cur][q];
+            if (B.d[e] != DONE) B.d[e] = B.scr[B.cls[q] & 0xFFFF];
+        }
+        __syncthreads();
+        mk(PH_BEXT);
         }
         first = false;
         {
             uint64_t kk[PER];
+            bool on[PER];
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const uint32_t q = tid + u * NT;
-                if (q < M && B.act[q]) {
+                on[u] = false;
+                if (q < M) {
                     const uint32_t e = B.ord[cur][q];
-                    kk[u] = key_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], B.d[e]);
+                    const uint32_t de = B.d[e];
+                    on[u] = de != DONE;
+                    if (on[u]) kk[u] = key_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], de);
                 }
             }
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const uint32_t q = tid + u * NT;
-                if (q < M && B.act[q]) B.key[B.ord[cur][q]] = kk[u];
-            }
+            for (int u = 0; u < PER; ++u)
+                if (on[u]) B.kq[tid + u * NT] = kk[u];
         }
         __syncthreads();
-        for (uint32_t q = tid; q < M; q += NT) {
-            const uint32_t e = B.ord[cur][q];
-            if (B.act[q]) {
-                const uint64_t k = B.key[e];
-                const uint32_t i = B.id[e];
-                const uint32_t c0 = B.cst[q];
-                uint32_t r = 0;
-                for (uint32_t j = c0; j < M && B.cst[j] == c0; ++j) {
-                    const uint32_t ee = B.ord[cur][j];
-                    const uint64_t kk = B.key[ee];
-                    r += (kk < k || (kk == k && B.id[ee] < i)) ? 1u : 0u;
+        mk(PH_BKEY);
+        // rank inside the class; the key run's first element also finds the
+        // largest smaller key (its new predecessor) for the lcp
+        {
+            uint32_t np[PER];
+            bool on[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t q = tid + u * NT;
+                on[u] = false;
+                if (q >= M) continue;
+                const uint32_t e = B.ord[cur][q];
+                np[u] = q;
+                if (B.d[e] == DONE) continue;
+                on[u] = true;
+                const uint32_t cl = B.cls[q], c0 = cl & 0xFFFF, c1 = cl >> 16;
+                const uint64_t k = B.kq[q];
+                uint32_t less = 0, eqb = 0, eqa = 0;
+                uint64_t ml = 0;
+                for (uint32_t j = c0; j < c1; ++j) {
+                    const uint64_t kj = B.kq[j];
+                    const bool lt = kj < k, eq = kj == k;
+                    less += lt ? 1u : 0u;
+                    eqa += eq ? 1u : 0u;
+                    eqb += (eq && j < q) ? 1u : 0u;
+                    ml = (lt && kj > ml) ? kj : ml;
                 }
-                B.ord[cur ^ 1][c0 + r] = (uint16_t)e;
-            } else {
-                B.ord[cur ^ 1][q] = (uint16_t)e;
+                np[u] = c0 + less + eqb;
+                const uint32_t de = B.d[e];
+                if (eqb == 0) {
+                    if (less && P.lcp) P.lcp[gpos(np[u])] = de + (uint32_t)(__clzll(k ^ ml) >> 3);
+                } else if ((k & 0xFF) == 0) {
+                    if (P.lcp) P.lcp[gpos(np[u])] = B.ln[e];
+                }
+                const bool go = eqa >= 2 && (k & 0xFF) != 0;
+                B.d[e] = go ? de + 8 : DONE;
+                if (go) B.any = 1;
+                // a run's first element marks a new class start
+                B.scr[np[u]] = eqb == 0 ? np[u] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t q = tid + u * NT;
+                if (q >= M) continue;
+                if (!on[u]) B.scr[q] = q;
+                B.ord[cur ^ 1][np[u]] = B.ord[cur][q];
             }
         }
         __syncthreads();
         cur ^= 1;
-        for (uint32_t q = tid; q < M; q += NT) {
-            const uint32_t e = B.ord[cur][q];
-            bool head = (q == B.cst[q]);
-            if (B.act[q] && !head) {
-                const uint32_t pe = B.ord[cur][q - 1];
-                const uint64_t k = B.key[e], pk = B.key[pe];
-                if (k != pk) {
-                    head = true;
-                    if (P.lcp) P.lcp[gpos(q)] = B.d[e] + (uint32_t)(__clzll(k ^ pk) >> 3);
-                } else if ((k & 0xFF) == 0) {
-                    if (P.lcp) P.lcp[gpos(q)] = B.ln[e];
-                }
-            }
-            B.scr[q] = head ? q : 0u;
-        }
-        __syncthreads();
-        block_scan(B.scr, (int)M, tmp, false, MaxOp(), 0u);
-        for (uint32_t q = tid; q < M; q += NT) {
-            const uint32_t nc = B.scr[q];
-            if (B.act[q]) {
-                const uint32_t e = B.ord[cur][q];
-                const bool two = (q > nc) || (q + 1 < M && B.scr[q + 1] == nc);
-                const bool go = two && ((B.key[e] & 0xFF) != 0);
-                B.act[q] = go ? 1 : 0;
-                if (go) {
-                    B.d[e] += 8;
-                    B.any = 1;
-                }
-            }
-        }
-        __syncthreads();
-        for (uint32_t q = tid; q < M; q += NT) B.cst[q] = (uint16_t)B.scr[q];
         more = uni(B.any) != 0;
+        if (more) {
+            // class starts by a max-scan over the run starts, class ends at
+            // each class's last position (kept in the key array meanwhile)
+            block_scan(B.scr, (int)M, tmp, false, MaxOp(), 0u);
+            uint32_t *cend = reinterpret_cast<uint32_t *>(B.kq);
+            for (uint32_t q = tid; q < M; q += NT)
+                if (q + 1 == M || B.scr[q + 1] != B.scr[q]) cend[B.scr[q]] = q + 1;
+            __syncthreads();
+            for (uint32_t q = tid; q < M; q += NT) B.cls[q] = B.scr[q] | (cend[B.scr[q]] << 16);
+        }
         __syncthreads();
         if (tid == 0) B.any = 0;
+        mk(PH_BRANK);
     }
     for (uint32_t q = tid; q < M; q += NT) P.perm[gpos(q)] = B.id[B.ord[cur][q]] - setbase;
+    if (tid == 0) {
+        const unsigned long long dt = wall_clock64() - t_start;
+        st[ST_CHUNKS] += 1;
+        st[ST_ROUNDS] += rounds;
+        st[ST_MAX_CHUNK] = max(st[ST_MAX_CHUNK], (dt << 24) | ((unsigned long long)min(rounds, 4095u) << 12) | M);
+    }
     __syncthreads();
 }
 
@@ -321,15 +457,22 @@ struct StepLDS {
     uint32_t bst[NBPAD];      // bucket start, relative to the segment
     uint32_t psz[NBPAD + 1];  // exclusive size prefix over the small buckets
     uint16_t lsmall[NBPAD];
-    uint16_t llarge[NBPAD];
-    uint16_t lident[NBPAD];
-    uint16_t cfirst[NBPAD + 1];
-    uint32_t nsmall, nlarge, nident, nchunk;
+    union {
+        struct {
+            uint16_t llarge[NBPAD];
+            uint16_t lident[NBPAD];   // identical buckets, later the publish rank of each chunk
+        };
+        uint32_t gdep[NBPAD];         // a published chunk's group depths
+    };
+    uint16_t cfirst[NBPAD + 1];       // first small bucket of each chunk (bit 15: published)
+    uint32_t nsmall, nlarge, nident, nchunk, npub, qfail;
+    unsigned long long dbase, qpos2;
     unsigned long long best;
     unsigned long long qpos;
-    unsigned long long ph[8];     // this workgroup's time per phase (thread 0)
+    unsigned long long ph[NPH];   // this workgroup's time per phase (thread 0)
+    unsigned long long st[NST];   // this workgroup's statistics (thread 0)
     unsigned long long ph_last;
-    uint32_t ext_min;
+    uint32_t ext_min, nlist;
     uint32_t tmp[NW];
     union {
         struct {
@@ -362,63 +505,64 @@ __device__ __forceinline__ uint32_t child_depth(const Split &sp, uint32_t h, uin
     return h + sp.hl[b >> 1];
 }
 
-struct SmallGroups {   // groups = consecutive entries of the step's small-bucket list
-    const uint32_t *hist, *bst, *psz;
-    const uint16_t *lsmall;
-    const Split *sp;
-    uint32_t k0, begin, pre0, h;
-    __device__ uint32_t gstart(uint32_t g) const { return begin + bst[lsmall[k0 + g]]; }
-    __device__ uint32_t gsize(uint32_t g) const { return hist[lsmall[k0 + g]]; }
-    __device__ uint32_t gdepth(uint32_t g) const { return child_depth(*sp, h, lsmall[k0 + g]); }
-    __device__ uint32_t gpre(uint32_t g) const { return psz[k0 + g] - pre0; }
-};
-
-struct OneGroup {
-    uint32_t start, size, depth;
-    __device__ uint32_t gstart(uint32_t) const { return start; }
-    __device__ uint32_t gsize(uint32_t) const { return size; }
-    __device__ uint32_t gdepth(uint32_t) const { return depth; }
-    __device__ uint32_t gpre(uint32_t) const { return 0; }
+struct DescGroups {   // a chunk's groups, unpacked from their descriptors into LDS
+    const uint32_t *start, *size, *depth, *pre;
+    __device__ uint32_t gstart(uint32_t g) const { return start[g]; }
+    __device__ uint32_t gsize(uint32_t g) const { return size[g]; }
+    __device__ uint32_t gdepth(uint32_t g) const { return depth[g]; }
+    __device__ uint32_t gpre(uint32_t g) const { return pre[g]; }
 };
 
 __device__ __forceinline__ unsigned long long uni64(unsigned long long x) {
     return ((unsigned long long)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
 }
 
-// Wait until queue position `pos` holds a task.  Executed by every lane of a
-// wave with wave-uniform values only (no loop inside a divergent region: a
-// spin loop run by one lane next to barriers can be lowered so that the other
-// lanes pass a barrier without it).  Polls with relaxed agent-scope loads (no
-// cache invalidation per poll), sleeps between polls, and issues one acquire
-// fence when the task is there.  Returns 1 (task ready), 0 (queue drained:
+// Wait until queue position `pos` holds a task.  Executed by every lane of one
+// wave with wave-uniform values only (no loop inside a lane-divergent region:
+// a spin loop run by one lane next to barriers can be lowered so that the
+// other lanes pass a barrier without it).  Polls with relaxed agent-scope
+// loads (no cache invalidation per poll), sleeps between polls with a growing
+// pause (up to about 4000 cycles), and issues one acquire fence when the task
+// is there.  Returns 1 (task ready), 0 (queue drained:
 // nothing pending, so nothing can be enqueued any more) or -1 (device error or
 // the wait limit, by wall clock or by poll count).
 __device__ __forceinline__ int poll_slot(const Params &P, Slot *s, unsigned long long pos) {
     const unsigned long long t0 = wall_clock64();
+    uint32_t nap = 1;
     for (unsigned long long it = 0;; ++it) {
         if (uni64(ld_rlx(&s->seq)) == pos + 1) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             return 1;
         }
-        if (uni64(ld_rlx(&P.ctl->pending)) == 0) return 0;
-        if (uni64(ld_rlx(&P.ctl->error)) != 0) return -1;
+        // the shared counters only every 8th poll (the slot is this
+        // workgroup's own line; the counters are everybody's)
+        if ((it & 7) == 7) {
+            if (uni64(ld_rlx(&P.ctl->pending)) == 0) return 0;
+            if (uni64(ld_rlx(&P.ctl->error)) != 0) return -1;
+        }
         if (wall_clock64() - t0 > P.limit_ticks || it > P.limit_iters) {
             if (lane_id() == 0)
                 __hip_atomic_fetch_or(&P.ctl->error, ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return -1;
         }
-        __builtin_amdgcn_s_sleep(10);
+        for (uint32_t k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(8);
+        nap = min(2 * nap, 8u);
     }
 }
 
-// Publish one task (already counted in `pending`) at queue position pos.  One
+// Publishing a task (already counted in `pending`) at queue position pos takes
+// two steps: stage() writes the slot's fields, and after the workgroup has
+// released its writes (release_wg: records, descriptors, slot fields),
+// commit() sets the slot's sequence number with a relaxed store.  One
 // attempt, no waiting: the ring is sized so that the slot's previous occupant
 // (pos - capacity) has long been consumed; if it has not, the sort fails with
-// a device error instead of overwriting it.
-__device__ __forceinline__ void publish(const Params &P, unsigned long long pos, const Task &t) {
+// a device error (and *fail is set, so that nothing is committed) instead of
+// overwriting it.
+__device__ __forceinline__ void stage(const Params &P, unsigned long long pos, const Task &t, uint32_t *fail) {
     Slot *s = &P.ring[pos & P.ring_mask];
     if (ld_rlx(&s->seq) != pos) {
         __hip_atomic_fetch_or(&P.ctl->error, ERR_QUEUE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *fail = 1;
         return;
     }
     s->begin = t.begin;
@@ -426,13 +570,15 @@ __device__ __forceinline__ void publish(const Params &P, unsigned long long pos,
     s->depth = t.depth;
     s->meta = t.meta;
     s->setbase = t.setbase;
-    st_rel(&s->seq, pos + 1);
+}
+__device__ __forceinline__ void commit(const Params &P, unsigned long long pos) {
+    st_rlx(&P.ring[pos & P.ring_mask].seq, pos + 1);
 }
 
 // Identical strings (an equality bucket whose splitter ends the string):
 // already in input-index order; lcp between them is their length.
 __device__ __forceinline__ void finish_ident(const Params &P, const Rec *src, uint32_t start, uint32_t cnt, uint32_t setbase) {
-    for (uint32_t i = threadIdx.x; i < cnt; i += NT) {
+    for (uint32_t i = tid_here(); i < cnt; i += NT) {
         const Rec r = src[start + i];
         P.perm[start + i] = r.id - setbase;
         if (P.lcp && i > 0) P.lcp[start + i] = r.ln;
@@ -443,42 +589,51 @@ __device__ __forceinline__ void finish_ident(const Params &P, const Rec *src, ui
 // `t` has been replaced by a child segment this workgroup continues with.
 template <int K, int C>
 __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int tid = tid_here(), w = tid >> 6, lane = tid & 63;
     const uint32_t begin = t.begin, S = t.size, meta = t.meta;
     uint32_t h = t.depth;
     auto kload = [&](uint32_t e, uint32_t hh) -> uint64_t {
         const Rec r = load_rec(P, meta, begin + e);
         return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
     };
+    // at most two samples: the second after a common-prefix extension (one
+    // call site keeps the persistent kernel's code small)
+#pragma nounroll
+    for (uint32_t pass = 0;; ++pass) {
     select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, P.equal, L.u.s.samp,
                      L.u.s.srt, L.u.s.fl, L.tmp, kload);
     mark(L, PH_SAMPLE);
-    if (uni(L.sp.ndistinct) == 1 && (splitter(L.sp, 0) & 0xFF) != 0) {
+    if (pass != 0 || uni(L.sp.ndistinct) != 1 || uni((uint32_t)(splitter(L.sp, 0) & 0xFF)) == 0) break;
+    {
         // Every sampled string has the same next 8 bytes: an equality chain.
         // Instead of one classification step per 8 equal bytes, find the
         // segment's exact common prefix (the minimum over its strings of the
         // LCP with its first string) and classify there.
-        if (tid == 0) L.ext_min = 0xFFFFFFFFu;
+        if (tid == 0) {
+            L.ext_min = 0xFFFFFFFFu;
+            L.nlist = 0;
+        }
         __syncthreads();
         const Rec f = load_rec(P, meta, begin);
         uint64_t fk[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) fk[i] = key_at(P.S.chars, P.S.nchars, f.st, f.ln, h + 8 * i);
+        keys32_at(P.S.chars, P.S.nchars, f.st, f.ln, h, fk);
+        uint32_t *list = reinterpret_cast<uint32_t *>(L.u.s.samp);   // 4 * NT entries
         // four strings per thread at a time: their records, then their first
-        // 32 bytes (16 independent loads), then the comparisons
-        for (uint32_t e0 = 1 + tid; e0 < S; e0 += 4 * NT) {
+        // 32 bytes (16 independent loads), then the comparisons; the strings
+        // equal to the first one on all 32 bytes go on in a list
+        for (uint32_t b0 = 1; b0 < S; b0 += 4 * NT) {
+            const uint32_t e0 = b0 + tid;
             Rec r[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (e0 + u * NT < S) r[u] = load_rec(P, meta, begin + e0 + u * NT);
             uint64_t k[4][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    k[u][i] = (e0 + u * NT < S) ? key_at(P.S.chars, P.S.nchars, r[u].st, r[u].ln, h + 8 * i) : 0;
+            for (int u = 0; u < 4; ++u) {
+                if (e0 + u * NT < S) keys32_at(P.S.chars, P.S.nchars, r[u].st, r[u].ln, h, k[u]);
+                else k[u][0] = k[u][1] = k[u][2] = k[u][3] = 0;
+            }
             uint32_t res = 0xFFFFFFFFu;
-            uint32_t more = 0;   // strings equal to the reference on all 32 bytes
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 bool done = e0 + u * NT >= S;
@@ -493,28 +648,39 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
                         done = true;
                     }
                 }
-                if (!done) more |= 1u << u;
+                if (!done) list[atomicAdd(&L.nlist, 1u)] = e0 + u * NT;
             }
-            while (more) {
-                const uint32_t u = __builtin_ctz(more);
-                more &= more - 1;
-                const Rec q = load_rec(P, meta, begin + e0 + u * NT);
-                res = min(res, lcp_from(P, f.st, f.ln, q.st, q.ln, h + 32, &L.ext_min));
+            if (res != 0xFFFFFFFFu) atomicMin(&L.ext_min, res);
+            __syncthreads();
+            const uint32_t n = uni(L.nlist);
+            __syncthreads();
+            if (tid == 0) L.nlist = 0;
+            const uint32_t gw = group_width(n);
+            if (gw) {
+                for (uint32_t i0 = 0; i0 < n; i0 += NT / gw) {
+                    const uint32_t i = i0 + tid / gw;
+                    const bool on = i < n;
+                    const Rec q = load_rec(P, meta, begin + (on ? list[i] : 0u));
+                    const uint32_t l = group_lcp(P, gw, on, f.st, f.ln, q.st, q.ln, h + 32, &L.ext_min);
+                    if (on && (tid & (gw - 1)) == 0) atomicMin(&L.ext_min, l);
+                }
+            } else {
+                for (uint32_t i = tid; i < n; i += NT) {
+                    const Rec q = load_rec(P, meta, begin + list[i]);
+                    atomicMin(&L.ext_min, lcp_from(P, f.st, f.ln, q.st, q.ln, h + 32, &L.ext_min));
+                }
             }
-            atomicMin(&L.ext_min, res);
+            __syncthreads();
         }
-        __syncthreads();
         h = uni(L.ext_min);
         mark(L, PH_EXTEND);
-        select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, P.equal, L.u.s.samp,
-                         L.u.s.srt, L.u.s.fl, L.tmp, kload);
-        mark(L, PH_SAMPLE);
+    }
     }
     for (int b = tid; b < NBPAD; b += NT) L.hist[b] = 0;
     if (tid == 0) {
-        __hip_atomic_fetch_add(&P.ctl->st_segments, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&P.ctl->st_strings, (unsigned long long)S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_max(&P.ctl->st_maxdepth, (unsigned long long)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        L.st[ST_SEGMENTS] += 1;
+        L.st[ST_STRINGS] += S;
+        L.st[ST_MAX_DEPTH] = max(L.st[ST_MAX_DEPTH], (unsigned long long)h);
     }
     __syncthreads();
     const uint32_t nb = uni(L.sp.nb);
@@ -568,8 +734,9 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
         }
         scatter_chunk<K>(L.u.sc, L.tmp, L.sp, m, r, min(CK, S - c0), L.u.sc.run, out, P.S.n, &P.ctl->error);
     }
-    // the redistributed records must be visible to every wave and every workgroup
-    __threadfence();
+    // the redistributed records are visible to this workgroup now; to the
+    // others with the one release before the tasks are committed
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     mark(L, PH_SCATTER);
 
@@ -580,6 +747,8 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
         L.nlarge = 0;
         L.nident = 0;
         L.best = 0;
+        L.qfail = 0;
+        L.npub = 0;
     }
     __syncthreads();
     for (uint32_t b = tid; b < nb; b += NT) {
@@ -626,10 +795,9 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
             if (k == keep) continue;
             const uint32_t b = L.llarge[k];
             Task c{begin + L.bst[b], L.hist[b], child_depth(L.sp, h, b), cpar, t.setbase};
-            publish(P, L.qpos + (k < keep ? k : k - 1), c);
+            stage(P, L.qpos + (k < keep ? k : k - 1), c, &L.qfail);
         }
     }
-    __syncthreads();
     // identical buckets
     const uint32_t nident = uni(L.nident);
     for (uint32_t k = 0; k < nident; ++k) {
@@ -637,8 +805,20 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
         finish_ident(P, out, begin + L.bst[b], L.hist[b], t.setbase);
     }
     __syncthreads();
-    mark(L, PH_CHILDREN);
-    // small buckets: base-case chunks of at most C strings, never splitting a group
+    // the child this workgroup goes on with (read before the chunks reuse
+    // the bucket arrays)
+    Task next{0, 0, 0, 0, 0};
+    if (nlarge >= 1) {
+        const uint32_t b = uni(L.llarge[keep]);
+        next = Task{begin + uni(L.bst[b]), uni(L.hist[b]), child_depth(L.sp, h, b), cpar, t.setbase};
+    }
+    // small buckets: base-case chunks of at most C strings, never splitting a
+    // group.  Every small bucket gets a group descriptor (at most one per
+    // group over the whole sort); chunks of at least cap / 2 strings become
+    // tasks of their own so that idle workgroups sort them, except the last
+    // one when this workgroup has no large child to go on with; the rest are
+    // sorted here after the step.
+    uint32_t nchunk = 0;
     if (nsmall) {
         const uint32_t cap = (P.tbase * 2 <= (uint32_t)C) ? (uint32_t)C - P.tbase : 0u;
         for (uint32_t k = tid; k < nsmall; k += NT) {
@@ -648,23 +828,71 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
             if (k == nsmall - 1) L.nchunk = ck + 1;
         }
         __syncthreads();
-        const uint32_t nchunk = uni(L.nchunk);
-        if (tid == 0) L.cfirst[nchunk] = (uint16_t)nsmall;
-        __syncthreads();
-        if (tid == 0)
-            __hip_atomic_fetch_add(&P.ctl->st_base, (unsigned long long)nsmall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (uint32_t c = 0; c < nchunk; ++c) {
-            const uint32_t k0 = uni(L.cfirst[c]), k1 = uni(L.cfirst[c + 1]);
-            SmallGroups g{L.hist, L.bst, L.psz, L.lsmall, &L.sp, k0, begin, L.psz[k0], h};
-            base_chunk<C>(P, L.u.base, L.tmp, out, t.setbase, k1 - k0, uni(L.psz[k1] - L.psz[k0]), g);
+        nchunk = uni(L.nchunk);
+        if (tid == 0) {
+            L.cfirst[nchunk] = (uint16_t)nsmall;
+            L.st[ST_BASE] += nsmall;
+            const unsigned long long db = add_agent(&P.ctl->desc_top, (unsigned long long)nsmall);
+            uint32_t npub = 0;
+            if (db + nsmall > P.desc_cap) {
+                atomicOr(&P.ctl->error, ERR_INTERNAL);
+                L.nchunk = 0;
+            } else if (cap) {
+                for (uint32_t c = 0; c < nchunk; ++c) {
+                    const uint32_t k0 = L.cfirst[c], k1 = L.cfirst[c + 1];
+                    const bool last = c + 1 == nchunk;
+                    if ((!last || nlarge >= 1) && L.psz[k1] - L.psz[k0] >= cap / 2) {
+                        L.lident[c] = (uint16_t)npub++;
+                        L.cfirst[c] = (uint16_t)(k0 | 0x8000u);
+                    }
+                }
+                if (npub) {
+                    add_agent(&P.ctl->pending, (unsigned long long)npub);
+                    L.qpos2 = add_agent(&P.ctl->tail, (unsigned long long)npub);
+                    L.st[ST_PUBCHUNKS] += npub;
+                }
+            }
+            L.dbase = db;
+            L.npub = npub;
         }
+        __syncthreads();
+        nchunk = uni(L.nchunk);
+        if (nchunk) {
+            const unsigned long long db = uni64(L.dbase);
+            for (uint32_t k = tid; k < nsmall; k += NT) {
+                const uint32_t b = L.lsmall[k];
+                P.desc[db + k] = GroupDesc{begin + L.bst[b], L.hist[b], child_depth(L.sp, h, b), 0u};
+            }
+            if (uni(L.npub)) {
+                for (uint32_t c = tid; c < nchunk; c += NT) {
+                    const uint32_t f0 = L.cfirst[c];
+                    if (!(f0 & 0x8000)) continue;
+                    const uint32_t k0 = f0 & 0x7FFF, k1 = L.cfirst[c + 1] & 0x7FFF;
+                    stage(P, L.qpos2 + L.lident[c],
+                          Task{(uint32_t)(db + k0), k1 - k0, L.psz[k1] - L.psz[k0], M_CHUNK | cpar, t.setbase},
+                          &L.qfail);
+                }
+            }
+        }
+    } else if (tid == 0) {
+        L.nchunk = 0;
+    }
+    // one release for the step's records, descriptors and slot fields, then
+    // the sequence numbers that hand the tasks over
+    const uint32_t npub = uni(L.npub);
+    if (nlarge > 1 || npub) {
+        release_wg();
+        if (!uni(L.qfail)) {
+            for (uint32_t k = tid; k + 1 < nlarge; k += NT) commit(P, L.qpos + k);
+            for (uint32_t k = tid; k < npub; k += NT) commit(P, L.qpos2 + k);
+        }
+    } else {
+        __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
-    mark(L, PH_BASE);
+    mark(L, PH_CHILDREN);
     if (nlarge >= 1) {
-        const uint32_t b = uni(L.llarge[keep]);
-        t = Task{begin + uni(L.bst[b]), uni(L.hist[b]), child_depth(L.sp, h, b), cpar, t.setbase};
-        __syncthreads();
+        t = next;
         return true;
     }
     return false;
@@ -680,23 +908,71 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
         mark(L, PH_CHILDREN);
         return;
     }
-    if (t.size <= P.tbase) {
+    const int tid = tid_here();
+    bool seg = false;              // t is a segment still to classify
+    uint32_t ud0 = 0, ung = 0;     // group descriptors to unpack next
+    uint32_t ng = 0;               // groups ready in the bucket arrays
+    uint32_t nchunk = 0, c = 0;    // chunks of the last step, the next to look at
+    unsigned long long db = 0;
+    const Rec *src = (t.meta & M_PARITY) ? P.R1 : P.R0;
+    if (t.meta & M_CHUNK) {
+        ud0 = t.begin;
+        ung = t.size;
+    } else if (t.size <= P.tbase) {
         if (t.meta & M_IDENT_SRC) {
             // a whole set small enough for the base case: stage its records first
-            for (uint32_t i = threadIdx.x; i < t.size; i += NT) P.R0[t.begin + i] = make_rec(P.S, t.begin + i);
+            for (uint32_t i = tid; i < t.size; i += NT) P.R0[t.begin + i] = make_rec(P.S, t.begin + i);
             __threadfence();
-            __syncthreads();
-            t.meta = 0;
+            src = P.R0;
         }
-        const Rec *src = (t.meta & M_PARITY) ? P.R1 : P.R0;
-        OneGroup g{t.begin, t.size, t.depth};
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&P.ctl->st_base, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, 1, t.size, g);
-        mark(L, PH_BASE);
-        return;
+        if (tid == 0) {
+            L.bst[0] = t.begin;
+            L.hist[0] = t.size;
+            L.psz[0] = t.size;
+            L.gdep[0] = t.depth;
+            L.st[ST_BASE] += 1;
+        }
+        __syncthreads();
+        ng = 1;
+    } else {
+        seg = true;
     }
-    while (seg_step<K, C>(P, t, L)) {
+    for (;;) {
+        if (ung) {
+            for (uint32_t g = tid; g < ung; g += NT) {
+                const GroupDesc d = P.desc[ud0 + g];
+                L.bst[g] = d.start;
+                L.hist[g] = d.size;
+                L.psz[g] = d.size;
+                L.gdep[g] = d.depth;
+            }
+            __syncthreads();
+            ng = ung;
+            ung = 0;
+        }
+        if (ng) {
+            const uint32_t M = uni(block_scan(L.psz, (int)ng, L.tmp, true, AddOp(), 0u));
+            DescGroups g{L.bst, L.hist, L.gdep, L.psz};
+            base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, ng, M, g, [&](int i) { mark(L, i); }, L.st);
+            mark(L, PH_BASE);
+            ng = 0;
+        }
+        // the last step's chunks that stayed here
+        while (c < nchunk && (uni(L.cfirst[c]) & 0x8000)) ++c;
+        if (c < nchunk) {
+            const uint32_t k0 = uni(L.cfirst[c]), k1 = uni(L.cfirst[c + 1]) & 0x7FFF;
+            ud0 = (uint32_t)(db + k0);
+            ung = k1 - k0;
+            ++c;
+            continue;
+        }
+        if (!seg) break;
+        const bool to1 = out_is_r1(t.meta);
+        seg = seg_step<K, C>(P, t, L);
+        src = to1 ? P.R1 : P.R0;
+        nchunk = uni(L.nchunk);
+        db = uni64(L.dbase);
+        c = 0;
     }
 }
 
@@ -704,10 +980,11 @@ template <int K, int C>
 __global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
     __shared__ StepLDS<K, C> L;
     __shared__ unsigned long long claim;
-    __shared__ int outcome[NW];
+    __shared__ int outcome;
     if (P.ctl->error) return;
     const int w = threadIdx.x >> 6;
-    if (threadIdx.x < 8) L.ph[threadIdx.x] = 0;
+    if (threadIdx.x < NPH) L.ph[threadIdx.x] = 0;
+    if (threadIdx.x < NST) L.st[threadIdx.x] = 0;
     if (threadIdx.x == 0) L.ph_last = wall_clock64();
     for (;;) {
         // a barrier between the previous task's thread-0 epilogue and this
@@ -719,32 +996,41 @@ __global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
         __syncthreads();
         const unsigned long long pos = uni64(claim);
         Slot *s = &P.ring[pos & P.ring_mask];
-        const int oc = poll_slot(P, s, pos);
-        if (lane_id() == 0) outcome[w] = oc;
+        // one wave polls, the others wait at the barrier
+        if (uni((uint32_t)w) == 0) {
+            const int oc = poll_slot(P, s, pos);
+            if (lane_id() == 0) outcome = oc;
+        }
         __syncthreads();
-        // waves agree unless one hit an error or the wait limit: then all stop
-        int o = 1;
-        for (int ww = 0; ww < NW; ++ww) o = min(o, outcome[ww]);
-        o = (int)uni((uint32_t)o);
-        mark(L, PH_WAIT);
+        const int o = (int)uni((uint32_t)outcome);
+        mark(L, o > 0 ? PH_WAIT : PH_DRAIN);
         if (o <= 0) break;
         const Task t{uni(s->begin), uni(s->size), uni(s->depth), uni(s->meta), uni(s->setbase)};
         __syncthreads();   // every wave has read the slot: hand it back to the ring
-        if (threadIdx.x == 0) st_rel(&s->seq, pos + P.ring_mask + 1);
+        if (threadIdx.x == 0) st_rlx(&s->seq, pos + P.ring_mask + 1);
+        const unsigned long long t_task = wall_clock64();
         if (t.begin > P.S.n || t.size > P.S.n - t.begin) {
             if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
         } else {
             run_task<K, C>(P, t, L);
         }
-        __threadfence();
+        if (threadIdx.x == 0)
+            L.st[ST_MAX_TASK] = max(L.st[ST_MAX_TASK], ((wall_clock64() - t_task) << 24) | min(t.size, 0xFFFFFFu));
+        // the task's outputs need no release: nothing in this launch reads
+        // them, and the launch's end makes them visible
         __syncthreads();
         mark(L, PH_OTHER);
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&P.ctl->pending, ~0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) add_agent(&P.ctl->pending, ~0ull);
     }
     __syncthreads();
-    if (threadIdx.x < 8)
+    if (threadIdx.x < NPH)
         __hip_atomic_fetch_add(&P.ctl->ph[threadIdx.x], L.ph[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < NST && L.st[threadIdx.x]) {
+        if (threadIdx.x >= ST_MAX_DEPTH)
+            __hip_atomic_fetch_max(&P.ctl->st[threadIdx.x], L.st[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_fetch_add(&P.ctl->st[threadIdx.x], L.st[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -778,8 +1064,9 @@ __global__ void k_init(Params P, uint32_t mode, unsigned long long cap) {
         c->tail = nroot;
         c->pending = nroot;
         c->error = 0;
-        c->st_segments = c->st_strings = c->st_base = c->st_maxdepth = 0;
-        for (int k = 0; k < 8; ++k) c->ph[k] = 0;
+        c->desc_top = 0;
+        for (int k = 0; k < NST; ++k) c->st[k] = 0;
+        for (int k = 0; k < NPH; ++k) c->ph[k] = 0;
         if (P.lcp && P.S.n) P.lcp[0] = 0;
     }
 }

@@ -47,10 +47,14 @@ class Tuning(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("segments", ctypes.c_uint64), ("strings", ctypes.c_uint64),
                 ("base_groups", ctypes.c_uint64), ("max_depth", ctypes.c_uint64),
-                ("phase_ticks", ctypes.c_uint64 * 8)]
+                ("phase_ticks", ctypes.c_uint64 * 16),
+                ("base_chunks", ctypes.c_uint64), ("base_rounds", ctypes.c_uint64),
+                ("max_task", ctypes.c_uint64), ("max_chunk", ctypes.c_uint64),
+                ("published_chunks", ctypes.c_uint64)]
 
 
-PHASES = ["wait", "sample", "classify", "scatter", "children", "base", "extend", "other"]
+PHASES = ["wait", "sample", "classify", "scatter", "children", "base", "extend", "other",
+          "base_extend", "base_keys", "base_rank", "drain"]
 
 
 class Job(ctypes.Structure):
@@ -257,7 +261,12 @@ class Sorter:
         st = Stats()
         _check(lib().ssort_stats(self._h, ctypes.byref(st), _stream(stream)), "ssort_stats")
         return {"segments": st.segments, "strings": st.strings, "base_groups": st.base_groups,
-                "max_depth": st.max_depth, "phase_ticks": dict(zip(PHASES, list(st.phase_ticks)))}
+                "max_depth": st.max_depth, "base_chunks": st.base_chunks, "base_rounds": st.base_rounds,
+                "published_chunks": st.published_chunks,
+                "max_task": {"ticks": st.max_task >> 24, "strings": st.max_task & 0xFFFFFF},
+                "max_chunk": {"ticks": st.max_chunk >> 24, "rounds": (st.max_chunk >> 12) & 0xFFF,
+                              "strings": st.max_chunk & 0xFFF},
+                "phase_ticks": dict(zip(PHASES, list(st.phase_ticks)))}
 
     def debug_step(self, s: DeviceStrings, depth: int = 0, stream=None) -> dict:
         torch = self._torch

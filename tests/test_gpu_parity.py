@@ -120,6 +120,23 @@ def test_long_common_prefix(sorter):
     assert_parity(sorter, W.from_list(strs), "shared prefix 700")
 
 
+@pytest.mark.parametrize("n", [3041, 200000])
+def test_few_long_shared_prefixes(sorter, n):
+    """A few strings share long prefixes (40..690 bytes) with the first one and
+    each other among many that differ early: short lists of long comparisons,
+    handled by lane groups in the segment and base-case extensions."""
+    rng = np.random.default_rng(n)
+    X = bytes(rng.integers(97, 123, size=700).astype(np.uint8))
+    strs = [b"ABCDEFGH" + X]
+    for i in range(n - 41):
+        s = b"ABCDEFGH"
+        if i % 150 == 0:
+            s += X[:int(rng.integers(40, 691))]
+        strs.append(s + bytes(rng.integers(97, 123, size=int(rng.integers(0, 31))).astype(np.uint8)))
+    strs += [b"ABCDEFGH" + X[:600] + bytes([int(rng.integers(97, 100))]) for _ in range(40)]
+    assert_parity(sorter, W.from_list(strs), f"few long prefixes {n}")
+
+
 def test_determinism(sorter):
     ss = W.plain(50000, seed=8)
     a = gpu_sort(sorter, ss)

@@ -1,6 +1,10 @@
 """The HIP kernels compile for gfx950 with every barrier-carrying loop closed
-by a lane-uniform back edge (see isa_barriers.py)."""
+by a lane-uniform back edge (see isa_barriers.py), without register spills in
+the persistent worker, and with the default worker's machine code small
+enough for the instruction cache (64 KiB, shared by two compute units): a
+worker that outgrows it thrashes the cache and every phase slows down."""
 import os
+import re
 import shutil
 import subprocess
 
@@ -11,19 +15,53 @@ from tests import isa_barriers
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.skipif(shutil.which("/opt/rocm/bin/hipcc") is None, reason="hipcc not installed")
-def test_no_barrier_in_lane_divergent_loop(tmp_path):
+MC = "/opt/rocm/llvm/bin/llvm-mc"
+READELF = "/opt/rocm/llvm/bin/llvm-readelf"
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    if shutil.which("/opt/rocm/bin/hipcc") is None:
+        pytest.skip("hipcc not installed")
     from paper_1403_2056_amd import build
-    out = tmp_path / "ssort.s"
+    out = tmp_path_factory.mktemp("isa") / "ssort.s"
     cmd = [build.HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", build.INCLUDE, "-I", build.CSRC, "-S", "--cuda-device-only", "-o", str(out),
            os.path.join(build.CSRC, "ssort_api.hip")]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
-    lines = out.read_text().splitlines()
+    return out
+
+
+def test_no_barrier_in_lane_divergent_loop(asm):
+    lines = asm.read_text().splitlines()
     kernels = list(isa_barriers.kernels(lines))
     assert len(kernels) >= 10
     bad = {k: b for k, body in kernels if (b := isa_barriers.check(body))}
     assert not bad, bad
     names = " ".join(k for k, _ in kernels)
     assert "k_worker" in names
+
+
+def test_worker_without_spills(asm):
+    text = asm.read_text()
+    blocks = re.findall(r"\.name:\s+(\S+)\n(?:.*\n){0,40}?\s+\.private_segment_fixed_size:\s+(\d+)", text)
+    workers = {n: int(sz) for n, sz in blocks if "k_worker" in n}
+    assert len(workers) == 4, workers
+    assert all(sz == 0 for sz in workers.values()), workers
+
+
+@pytest.mark.skipif(not (os.path.exists(MC) and os.path.exists(READELF)), reason="llvm-mc not installed")
+def test_worker_code_fits_instruction_cache(asm, tmp_path):
+    obj = tmp_path / "ssort.o"
+    subprocess.check_call([MC, "-triple=amdgcn-amd-amdhsa", "-mcpu=gfx950", "-filetype=obj", str(asm), "-o", str(obj)],
+                          stderr=subprocess.DEVNULL)
+    syms = subprocess.run([READELF, "-s", "--wide", str(obj)], capture_output=True, text=True, check=True).stdout
+    size = {}
+    for ln in syms.splitlines():
+        f = ln.split()
+        if len(f) >= 8 and f[3] == "FUNC" and "k_worker" in f[7]:
+            size[f[7]] = int(f[2])
+    assert len(size) == 4, size
+    default = [v for k, v in size.items() if "ILi4ELi512E" in k]
+    assert default and default[0] < 64 * 1024, size
