@@ -26,7 +26,6 @@ struct ssort_ctx {
 
 namespace {
 
-constexpr uint32_t ROOT_MULTI_MIN = 1u << 16;   // whole-GPU root step above this size
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -37,43 +36,47 @@ uint64_t next_pow2(uint64_t x) {
 }
 
 struct Layout {
-    size_t ctl, r0, r1, bkt, ring, split, hist, totals, desc, total;
+    size_t ctl, r0, r1, bkt, ring, lseg[LMAX], t2s[LMAX], lsplit[LMAX], ltot[LMAX], hist, desc, total;
     uint64_t cap;
-    uint32_t ntiles;
+    uint32_t maxseg, maxtiles, tile;
 };
 
 Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     Layout L;
     const uint32_t K = c->tun.keys_per_thread;
-    const uint64_t tile = (uint64_t)NT * K * ROOT_CHUNKS;
-    L.ntiles = n ? (uint32_t)((n + tile - 1) / tile) : 0u;
-    // queued tasks are segments of more than base_threshold strings (at most
-    // two per such disjoint set of strings), the root tasks and published
-    // base-case chunks of at least (chunk - threshold) / 2 >= 128 strings;
-    // twice that bound leaves every slot's previous occupant consumed long
-    // before the slot is reused
-    const uint64_t live = 2 * (uint64_t)n / (c->tun.base_threshold + 1) + (uint64_t)n / 128 + m + NBMAX +
-                          (uint64_t)c->worker_blocks;
+    L.tile = (uint32_t)NT * K * ROOT_CHUNKS;
+    // a level holds segments of more than LVL_MIN strings (level 0: the input
+    // or sets of more than ROOT_MIN > LVL_MIN), and their tiles
+    L.maxseg = n / LVL_MIN + 1;
+    L.maxtiles = n / L.tile + L.maxseg;
+    // queued tasks: segments of more than base_threshold strings (at most
+    // two per such disjoint set of strings), the batched sets, base-case
+    // chunks (of at least (chunk - threshold) / 2 >= 128 strings when formed
+    // in a worker step; at most one per bucket when formed by a level); twice
+    // that bound leaves every slot's previous occupant consumed long before
+    // the slot is reused
+    const uint64_t live = 2 * (uint64_t)n / (c->tun.base_threshold + 1) + (uint64_t)n / 128 + m +
+                          (uint64_t)NBMAX * (2 * L.maxseg + 1) + (uint64_t)c->worker_blocks;
     L.cap = next_pow2(2 * live + 1024);
     size_t off = 0;
-    L.ctl = off;
-    off = align_up(off + sizeof(Ctl), 256);
-    L.r0 = off;
-    off = align_up(off + sizeof(Rec) * (size_t)n, 256);
-    L.r1 = off;
-    off = align_up(off + sizeof(Rec) * (size_t)n, 256);
-    L.bkt = off;
-    off = align_up(off + 2 * (size_t)n, 256);
-    L.ring = off;
-    off = align_up(off + sizeof(Slot) * (size_t)L.cap, 256);
-    L.split = off;
-    off = align_up(off + sizeof(Split), 256);
-    L.hist = off;
-    off = align_up(off + 4 * (size_t)NBPAD * L.ntiles, 256);
-    L.totals = off;
-    off = align_up(off + 4 * (size_t)NBPAD, 256);
-    L.desc = off;   // at most one descriptor per base-case group
-    off = align_up(off + sizeof(GroupDesc) * (size_t)n, 256);
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    L.ctl = take(sizeof(Ctl));
+    L.r0 = take(sizeof(Rec) * (size_t)n);
+    L.r1 = take(sizeof(Rec) * (size_t)n);
+    L.bkt = take(2 * (size_t)n);
+    L.ring = take(sizeof(Slot) * (size_t)L.cap);
+    for (int l = 0; l < LMAX; ++l) {
+        L.lseg[l] = take(sizeof(LvlSeg) * (size_t)L.maxseg);
+        L.t2s[l] = take(4 * (size_t)L.maxtiles);
+        L.lsplit[l] = take(sizeof(Split) * (size_t)L.maxseg);
+        L.ltot[l] = take(4 * (size_t)NBPAD * L.maxseg);
+    }
+    L.hist = take(4 * (size_t)NBPAD * L.maxtiles);
+    L.desc = take(sizeof(GroupDesc) * (size_t)n);   // at most one descriptor per base-case group
     L.total = off;
     return L;
 }
@@ -120,15 +123,20 @@ void launch_worker(const ssort_ctx *c, const Params &P, uint32_t grid, hipStream
     }
 }
 
-void launch_root(const ssort_ctx *c, const Params &P, uint32_t ntiles, uint32_t depth, bool schedule,
-                 hipStream_t s) {
-    hipLaunchKernelGGL(k_root_sample, dim3(1), dim3(NT), 0, s, P, depth);
-    if (c->tun.keys_per_thread == 4) hipLaunchKernelGGL((k_root_classify<4>), dim3(ntiles), dim3(NT), 0, s, P, depth);
-    else hipLaunchKernelGGL((k_root_classify<8>), dim3(ntiles), dim3(NT), 0, s, P, depth);
-    hipLaunchKernelGGL(k_root_colscan, dim3((NBMAX + CS_B - 1) / CS_B), dim3(NT), 0, s, P);
-    if (c->tun.keys_per_thread == 4) hipLaunchKernelGGL((k_root_scatter<4>), dim3(ntiles), dim3(NT), 0, s, P);
-    else hipLaunchKernelGGL((k_root_scatter<8>), dim3(ntiles), dim3(NT), 0, s, P);
-    if (schedule) hipLaunchKernelGGL(k_root_schedule, dim3(1), dim3(NT), 0, s, P, depth);
+// The whole-GPU levels (grids sized for each level's capacity; workgroups
+// beyond the level's actual count exit at once).  With schedule = false only
+// level 0 runs, without turning its buckets into tasks (the debug step).
+void launch_levels(const ssort_ctx *c, const Params &P, const Layout &L, bool schedule, hipStream_t s) {
+    const int K = c->tun.keys_per_thread;
+    for (uint32_t l = 0; l < (schedule ? (uint32_t)LMAX : 1u); ++l) {
+        hipLaunchKernelGGL(k_lvl_sample, dim3(L.maxseg), dim3(NT), 0, s, P, l);
+        if (K == 4) hipLaunchKernelGGL((k_lvl_classify<4>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
+        else hipLaunchKernelGGL((k_lvl_classify<8>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
+        hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), dim3(NT), 0, s, P, l);
+        if (K == 4) hipLaunchKernelGGL((k_lvl_scatter<4>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
+        else hipLaunchKernelGGL((k_lvl_scatter<8>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
+        if (schedule) hipLaunchKernelGGL(k_lvl_schedule, dim3(L.maxseg), dim3(NT), 0, s, P, l);
+    }
 }
 
 ssort_status check_strings(const ssort_strings *in) {
@@ -160,14 +168,21 @@ Params make_params(const ssort_ctx *c, const ssort_strings *in, uint32_t *perm, 
     P.ring = (Slot *)(w + L.ring);
     P.ring_mask = L.cap - 1;
     P.ctl = (Ctl *)(w + L.ctl);
-    P.gsplit = (Split *)(w + L.split);
+    for (int l = 0; l < LMAX; ++l) {
+        P.lseg[l] = (LvlSeg *)(w + L.lseg[l]);
+        P.tile2seg[l] = (uint32_t *)(w + L.t2s[l]);
+        P.lsplit[l] = (Split *)(w + L.lsplit[l]);
+        P.ltot[l] = (uint32_t *)(w + L.ltot[l]);
+    }
     P.hist = (uint32_t *)(w + L.hist);
-    P.totals = (uint32_t *)(w + L.totals);
     P.desc = (GroupDesc *)(w + L.desc);
     P.desc_cap = in->n;
     P.set_begin = set_begin;
     P.m = m;
-    P.ntiles = L.ntiles;
+    P.lmaxseg = L.maxseg;
+    P.lmaxtiles = L.maxtiles;
+    P.tile = L.tile;
+    P.chunk = (uint32_t)chunk_for(c->tun.base_threshold);
     P.tbase = c->tun.base_threshold;
     P.vmax = c->tun.v;
     P.equal = (c->tun.flags & SSORT_EQUAL) ? 1u : 0u;
@@ -298,14 +313,13 @@ ssort_status ssort_sort(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_p
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
     Params P = make_params(ctx, in, out_perm, out_lcp, ws, L, 1, nullptr);
-    const bool multi = in->n > ROOT_MULTI_MIN;
     if (ctx->prof) (void)hipEventRecord(ctx->ev[0], s);
-    hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, multi ? 0u : 1u,
-                       (unsigned long long)L.cap);
+    hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, (unsigned long long)L.cap);
     if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
-    if (multi) launch_root(ctx, P, L.ntiles, 0, true, s);
+    hipLaunchKernelGGL(k_seed, dim3(1), dim3(NT), 0, s, P, 1u, 0u, 0u);
+    if (in->n > ROOT_MIN) launch_levels(ctx, P, L, true, s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[1], s);
-    launch_worker(ctx, P, worker_grid(ctx, in->n, multi ? NBMAX : 1), s);
+    launch_worker(ctx, P, worker_grid(ctx, in->n, in->n > ROOT_MIN ? NBMAX : 1), s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[2], s);
     if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[3], s);
@@ -326,9 +340,10 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
     if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
     Params P = make_params(ctx, flat, out_perm, out_lcp, ws, L, m, set_begin);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[0], s);
-    hipLaunchKernelGGL(k_init, dim3(grid_for(std::max<uint64_t>(L.cap, m))), dim3(NT), 0, s, P, 2u,
-                       (unsigned long long)L.cap);
+    hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, (unsigned long long)L.cap);
     if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
+    hipLaunchKernelGGL(k_seed, dim3(grid_for(m)), dim3(NT), 0, s, P, 2u, 0u, 0u);
+    if (flat->n > ROOT_MIN) launch_levels(ctx, P, L, true, s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[1], s);
     launch_worker(ctx, P, worker_grid(ctx, flat->n, m), s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[2], s);
@@ -385,8 +400,9 @@ ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t 
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
     Params P = make_params(ctx, in, perm, nullptr, ws, L, 1, nullptr);
-    hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, 0u, (unsigned long long)L.cap);
-    launch_root(ctx, P, L.ntiles, depth, false, s);
+    hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, (unsigned long long)L.cap);
+    hipLaunchKernelGGL(k_seed, dim3(1), dim3(NT), 0, s, P, 1u, depth, 1u);
+    launch_levels(ctx, P, L, false, s);
     hipLaunchKernelGGL(k_debug_dump, dim3(grid_for(in->n)), dim3(NT), 0, s, P, depth, keys, split, tree, info, bucket,
                        hist, perm);
     ctx->last_ws = ws;

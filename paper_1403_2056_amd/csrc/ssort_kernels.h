@@ -7,6 +7,22 @@ namespace ssd {
 constexpr int NPH = 16;
 constexpr int NST = 9;
 
+// Whole-GPU steps: segments of more than LVL_MIN strings (the input itself,
+// or a batched set, when larger than ROOT_MIN) are classified and
+// redistributed by every workgroup of the GPU at once, LMAX levels deep,
+// before the persistent workers take over.
+constexpr int LMAX = 2;
+constexpr uint32_t ROOT_MIN = 1u << 16;
+constexpr uint32_t LVL_MIN = 1u << 15;
+
+// One segment of a whole-GPU level: its strings, depth and record source,
+// and its tiles (ROOT_CHUNKS chunks of NT*K strings each) in the level's tile
+// numbering.
+struct __align__(32) LvlSeg {
+    uint32_t begin, size, depth, meta;
+    uint32_t tile0, ntile, setbase, pad;
+};
+
 // Control block at the start of the workspace.  The queue counters each
 // sit on a cache line of their own: every idle workgroup polls `pending`,
 // and traffic to one line is served by one L2 channel, whose congestion
@@ -18,6 +34,7 @@ struct Ctl {
     alignas(128) unsigned long long pending;   // tasks enqueued or running, not finished
     alignas(128) unsigned long long error;     // bit mask of device errors
     alignas(128) unsigned long long desc_top;  // group descriptors handed out
+    alignas(128) unsigned long long lvl[LMAX][2];   // whole-GPU levels: segments, tiles
     alignas(128) unsigned long long st[NST];   // statistics (ST_*)
     unsigned long long ph[NPH];                // worker time per phase, wall-clock ticks summed over workgroups
 };
@@ -66,21 +83,24 @@ struct Params {
     Slot *ring;
     unsigned long long ring_mask;
     Ctl *ctl;
-    Split *gsplit;           // root step splitters (global copy)
-    uint32_t *hist;          // root step tile histograms, bucket-major [nb][ntiles]
-    uint32_t *totals;        // root step bucket totals [NBPAD]
+    LvlSeg *lseg[LMAX];      // whole-GPU levels: segments
+    uint32_t *tile2seg[LMAX];   // tile -> segment
+    Split *lsplit[LMAX];     // splitters per segment
+    uint32_t *ltot[LMAX];    // bucket totals per segment [seg][NBPAD]
+    uint32_t *hist;          // tile histograms of the current level, tile-major [tile][NBPAD]
     GroupDesc *desc;         // base-case group descriptors (at most one per group)
     uint64_t desc_cap;
     const uint32_t *set_begin;   // batched: m+1 set boundaries, else null
     uint32_t m;              // number of sets (1 for a plain sort)
-    uint32_t ntiles;
+    uint32_t lmaxseg, lmaxtiles;   // capacity of each level's segment and tile arrays
+    uint32_t tile;           // strings per tile (ROOT_CHUNKS * NT * K)
+    uint32_t chunk;          // base-case chunk capacity C
     uint32_t tbase;
     uint32_t vmax;
     uint32_t equal;          // S5-Equal classification
     unsigned long long limit_ticks;
     unsigned long long limit_iters;
-    uint32_t dbg;            // debug step: stop after the root redistribution
-    uint32_t pad;
+
 };
 
 }  // namespace ssd

@@ -1,16 +1,21 @@
 // HIP kernels of the string sample sorter for gfx950.
 //
 // Control flow of one sort (all enqueued on one stream, no host round trip):
-//   k_init            queue ring, control block, root task(s)
-//   [root step]       for large inputs the first classification step runs
-//                     across the whole GPU: k_root_sample (one workgroup),
-//                     k_root_classify (tiles), k_root_colscan (per bucket),
-//                     k_root_scatter (tiles), k_root_schedule (one workgroup)
+//   k_init            queue ring, control block
+//   k_seed            the input (or each batched set): a segment of the first
+//                     whole-GPU level when large, else a worker task
+//   [levels 0, 1]     large segments are classified by the whole GPU:
+//                     k_lvl_sample (a workgroup per segment), k_lvl_classify
+//                     (tiles), k_lvl_colscan (per segment and bucket),
+//                     k_lvl_scatter (tiles), k_lvl_schedule (a workgroup per
+//                     segment: next-level segments, worker tasks, base-case
+//                     chunk tasks)
 //   k_worker          persistent workgroups drain a device-side work queue of
-//                     segments; each segment step (sample, tree, classify,
-//                     count, prefix sum, stable redistribution) is done by one
-//                     workgroup, small children go to the LCP-aware base case
-//                     right away, large children are queued (one is kept)
+//                     segments and base-case chunks; each segment step
+//                     (sample, tree, classify, count, prefix sum, stable
+//                     redistribution) is done by one workgroup, its large
+//                     children are queued (one is kept), its small buckets go
+//                     to the LCP-aware base case in chunks, queued as well
 //   k_seam            LCPs at bucket boundaries from the separation depth
 //                     recorded when the boundary was created
 #include "ssort_kernels.h"
@@ -1034,40 +1039,21 @@ __global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation: queue ring sequence numbers, control block, root tasks.
-// mode 0: no root task (the whole-GPU root step follows), 1: one root task for
-// [0, n), 2: one root task per set of a batch.
-__global__ void k_init(Params P, uint32_t mode, unsigned long long cap) {
+// Initialisation: queue ring sequence numbers and the control block.
+__global__ void k_init(Params P, unsigned long long cap) {
     const unsigned long long i0 = blockIdx.x * (unsigned long long)NT + threadIdx.x;
     const unsigned long long stride = (unsigned long long)gridDim.x * NT;
-    const uint32_t nroot = mode == 0 ? 0u : (mode == 1 ? 1u : P.m);
-    for (unsigned long long i = i0; i < cap; i += stride) {
-        Slot *s = &P.ring[i];
-        if (i < nroot) {
-            uint32_t b, e;
-            if (mode == 1) { b = 0; e = P.S.n; }
-            else { b = P.set_begin[i]; e = P.set_begin[i + 1]; }
-            s->begin = b;
-            s->size = e - b;
-            s->depth = 0;
-            s->meta = M_IDENT_SRC;
-            s->setbase = mode == 2 ? b : 0u;
-            s->seq = i + 1;
-            if (P.lcp && e > b) P.lcp[b] = 0;
-        } else {
-            s->seq = i;
-        }
-    }
+    for (unsigned long long i = i0; i < cap; i += stride) P.ring[i].seq = i;
     if (i0 == 0) {
         Ctl *c = P.ctl;
         c->head = 0;
-        c->tail = nroot;
-        c->pending = nroot;
+        c->tail = 0;
+        c->pending = 0;
         c->error = 0;
         c->desc_top = 0;
+        for (int l = 0; l < LMAX; ++l) c->lvl[l][0] = c->lvl[l][1] = 0;
         for (int k = 0; k < NST; ++k) c->st[k] = 0;
         for (int k = 0; k < NPH; ++k) c->ph[k] = 0;
-        if (P.lcp && P.S.n) P.lcp[0] = 0;
     }
 }
 
@@ -1097,7 +1083,73 @@ __global__ void k_validate(Params P) {
 
 // ---------------------------------------------------------------------------
 // Root step across the whole GPU (the fully parallel step of pS5).
-struct RootSampleLDS {
+// ---------------------------------------------------------------------------
+// Whole-GPU levels.  Every segment of a level is classified and redistributed
+// by the whole GPU: one workgroup samples each segment (k_lvl_sample), tiles
+// of every segment are classified in parallel with per-tile histograms
+// (k_lvl_classify), the histograms are scanned per segment and bucket
+// (k_lvl_colscan), the tiles redistribute their records (k_lvl_scatter), and
+// one workgroup per segment turns its buckets into the next level's segments,
+// worker tasks and base-case chunk tasks (k_lvl_schedule).  A grid is sized
+// for the level's capacity; workgroups beyond the level's count exit.
+
+// Records of a segment: from the input (identity) or from a record buffer.
+__device__ __forceinline__ Rec seg_rec(const Params &P, uint32_t meta, uint32_t i) {
+    if (meta & M_IDENT_SRC) return make_rec(P.S, i);
+    return ((meta & M_PARITY) ? P.R1 : P.R0)[i];
+}
+
+// Append a segment to level l (its tiles get consecutive numbers).
+__device__ void lvl_append(const Params &P, uint32_t l, const LvlSeg &g0) {
+    LvlSeg g = g0;
+    g.ntile = (g.size + P.tile - 1) / P.tile;
+    const unsigned long long idx = add_agent(&P.ctl->lvl[l][0], 1ull);
+    const unsigned long long t0 = add_agent(&P.ctl->lvl[l][1], (unsigned long long)g.ntile);
+    if (idx >= P.lmaxseg || t0 + g.ntile > P.lmaxtiles) {
+        atomicOr(&P.ctl->error, ERR_INTERNAL);
+        return;
+    }
+    g.tile0 = (uint32_t)t0;
+    P.lseg[l][idx] = g;
+    for (uint32_t j = 0; j < g.ntile; ++j) P.tile2seg[l][t0 + j] = (uint32_t)idx;
+}
+
+// Put a worker task at a queue position reserved before the workers start
+// (the launch boundary orders it before any read).
+__device__ __forceinline__ void seed_task(const Params &P, unsigned long long pos, const Task &t) {
+    Slot *s = &P.ring[pos & P.ring_mask];
+    s->begin = t.begin;
+    s->size = t.size;
+    s->depth = t.depth;
+    s->meta = t.meta;
+    s->setbase = t.setbase;
+    s->seq = pos + 1;
+}
+
+__device__ __forceinline__ uint32_t lvl_count(const Params &P, uint32_t l, int which) {
+    return (uint32_t)min(P.ctl->lvl[l][which], which ? (unsigned long long)P.lmaxtiles : (unsigned long long)P.lmaxseg);
+}
+
+// Level 0: the whole input (mode 1) or every batched set (mode 2); a segment
+// of at most ROOT_MIN strings (unless force) goes straight to the workers.
+__global__ void k_seed(Params P, uint32_t mode, uint32_t depth, uint32_t force) {
+    if (P.ctl->error) return;
+    const uint32_t nset = mode == 1 ? 1u : P.m;
+    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < nset; i += gridDim.x * NT) {
+        const uint32_t b = mode == 1 ? 0u : P.set_begin[i], e = mode == 1 ? P.S.n : P.set_begin[i + 1];
+        if (e <= b) continue;
+        if (P.lcp) P.lcp[b] = 0;
+        const uint32_t setbase = mode == 2 ? b : 0u;
+        if (force || e - b > ROOT_MIN) {
+            lvl_append(P, 0, LvlSeg{b, e - b, depth, M_IDENT_SRC, 0, 0, setbase, 0});
+        } else {
+            add_agent(&P.ctl->pending, 1ull);
+            seed_task(P, add_agent(&P.ctl->tail, 1ull), Task{b, e - b, depth, M_IDENT_SRC, setbase});
+        }
+    }
+}
+
+struct LvlSampleLDS {
     Split sp;
     uint64_t samp[SAMPLE_MAX + 1];
     uint64_t srt[SAMPLE_MAX + 1];
@@ -1105,16 +1157,18 @@ struct RootSampleLDS {
     uint32_t tmp[NW];
 };
 
-__global__ __launch_bounds__(NT) void k_root_sample(Params P, uint32_t depth) {
-    __shared__ RootSampleLDS L;
-    if (P.ctl->error) return;
+__global__ __launch_bounds__(NT) void k_lvl_sample(Params P, uint32_t l) {
+    __shared__ LvlSampleLDS L;
+    if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 0)) return;
+    const LvlSeg g = P.lseg[l][blockIdx.x];
     auto kload = [&](uint32_t e, uint32_t hh) -> uint64_t {
-        const Rec r = make_rec(P.S, e);
+        const Rec r = seg_rec(P, g.meta, g.begin + e);
         return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
     };
-    select_splitters(L.sp, P.S.n, depth, 0x2545F491u ^ P.S.n, P.vmax, P.equal, L.samp, L.srt, L.fl, L.tmp, kload);
+    select_splitters(L.sp, g.size, g.depth, hash32(g.begin * 0x85EBCA6Bu ^ g.depth * 0xC2B2AE35u ^ g.size), P.vmax,
+                     P.equal, L.samp, L.srt, L.fl, L.tmp, kload);
     const uint32_t *src = (const uint32_t *)&L.sp;
-    uint32_t *dst = (uint32_t *)P.gsplit;
+    uint32_t *dst = (uint32_t *)&P.lsplit[l][blockIdx.x];
     for (uint32_t i = threadIdx.x; i < sizeof(Split) / 4; i += NT) dst[i] = src[i];
 }
 
@@ -1126,62 +1180,70 @@ __device__ void load_split(Split &sp, const Split *g) {
 }
 
 template <int K>
-__global__ __launch_bounds__(NT) void k_root_classify(Params P, uint32_t depth) {
+__global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
     __shared__ Split sp;
     __shared__ uint32_t hist[NBPAD];
-    if (P.ctl->error) return;
-    load_split(sp, P.gsplit);
+    if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 1)) return;
+    const uint32_t seg = P.tile2seg[l][blockIdx.x];
+    const LvlSeg g = P.lseg[l][seg];
+    load_split(sp, &P.lsplit[l][seg]);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     for (int b = tid; b < NBPAD; b += NT) hist[b] = 0;
     __syncthreads();
-    const uint32_t n = P.S.n, nb = uni(sp.nb);
+    const uint32_t nb = uni(sp.nb);
     const int nbits = (int)uni(sp.nbits);
+    const uint32_t lt = blockIdx.x - g.tile0;
     // one tile = ROOT_CHUNKS chunks of NT*K strings, classified chunk by chunk
     for (uint32_t ch = 0; ch < ROOT_CHUNKS; ++ch) {
-        const uint32_t c0 = (blockIdx.x * ROOT_CHUNKS + ch) * (uint32_t)(NT * K);
-        if (c0 >= n) break;
+        const uint32_t c0 = (lt * ROOT_CHUNKS + ch) * (uint32_t)(NT * K);
+        if (c0 >= g.size) break;
         Rec r[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-            if (e < n) r[j] = make_rec(P.S, e);
+            if (e < g.size) r[j] = seg_rec(P, g.meta, g.begin + e);
         }
         uint64_t k[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-            k[j] = e < n ? key_at(P.S.chars, P.S.nchars, r[j].st, r[j].ln, depth) : 0;
+            k[j] = e < g.size ? key_at(P.S.chars, P.S.nchars, r[j].st, r[j].ln, g.depth) : 0;
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-            const bool valid = e < n;
+            const bool valid = e < g.size;
             const uint32_t m = valid ? classify_any(k[j], sp) : nb;
             const uint64_t mask = match_any(m, nbits);
             if (valid && lane == 63 - (int)__clzll(mask)) atomicAdd(&hist[m], (uint32_t)__popcll(mask));
-            if (valid) P.bkt[e] = (uint16_t)m;
+            if (valid) P.bkt[g.begin + e] = (uint16_t)m;
         }
     }
     __syncthreads();
     for (uint32_t b = tid; b < nb; b += NT) P.hist[(size_t)blockIdx.x * NBPAD + b] = hist[b];
 }
 
-// Exclusive scan over the tiles, per bucket, of the tile histograms (stored
-// tile-major: one contiguous row of counters per tile), giving every (tile,
-// bucket) pair its offset inside the bucket, and the bucket totals.  A
-// workgroup owns 16 buckets; thread t handles bucket 16g + t%16 over the tile
-// range t/16, so 16 neighbouring threads read one 64-byte run of a row.
+// Exclusive scan over a segment's tiles, per bucket, of the tile histograms
+// (stored tile-major: one contiguous row of counters per tile), giving every
+// (tile, bucket) pair its offset inside the bucket, and the bucket totals.  A
+// workgroup owns 16 buckets of one segment; thread t handles bucket 16g +
+// t%16 over the tile range t/16, so 16 neighbouring threads read one 64-byte
+// run of a row.
 constexpr int CS_B = 16;
 constexpr int CS_R = NT / CS_B;
-__global__ __launch_bounds__(NT) void k_root_colscan(Params P) {
+constexpr int CS_G = NBPAD / CS_B;   // bucket groups per segment
+__global__ __launch_bounds__(NT) void k_lvl_colscan(Params P, uint32_t l) {
     __shared__ uint32_t part[CS_R][CS_B];
-    if (P.ctl->error) return;
-    const uint32_t nb = uni(P.gsplit->nb);
-    const uint32_t b = blockIdx.x * CS_B + (threadIdx.x % CS_B);
+    const uint32_t seg = blockIdx.x / CS_G, grp = blockIdx.x % CS_G;
+    if (P.ctl->error || seg >= lvl_count(P, l, 0)) return;
+    const LvlSeg g = P.lseg[l][seg];
+    const uint32_t nb = uni(P.lsplit[l][seg].nb);
+    if (grp * CS_B >= nb) return;
+    const uint32_t b = grp * CS_B + (threadIdx.x % CS_B);
     const uint32_t r = threadIdx.x / CS_B;
-    const uint32_t T = P.ntiles;
+    const uint32_t T = g.ntile;
     const uint32_t per = (T + CS_R - 1) / CS_R;
-    const uint32_t lo = min(T, r * per), hi = min(T, lo + per);
+    const uint32_t lo = g.tile0 + min(T, r * per), hi = g.tile0 + min(T, r * per + per);
     uint32_t s = 0;
     if (b < nb) {
 #pragma unroll 8
@@ -1196,8 +1258,8 @@ __global__ __launch_bounds__(NT) void k_root_colscan(Params P) {
             part[k][threadIdx.x] = run;
             run += x;
         }
-        const uint32_t bb = blockIdx.x * CS_B + threadIdx.x;
-        if (bb < nb) P.totals[bb] = run;
+        const uint32_t bb = grp * CS_B + threadIdx.x;
+        if (bb < nb) P.ltot[l][(size_t)seg * NBPAD + bb] = run;
     }
     __syncthreads();
     if (b < nb) {
@@ -1212,7 +1274,7 @@ __global__ __launch_bounds__(NT) void k_root_colscan(Params P) {
 }
 
 template <int K>
-struct RootScatterLDS {
+struct LvlScatterLDS {
     Split sp;
     uint32_t run[NBPAD];
     uint32_t tmp[NW];
@@ -1220,70 +1282,154 @@ struct RootScatterLDS {
 };
 
 template <int K>
-__global__ __launch_bounds__(NT) void k_root_scatter(Params P) {
-    __shared__ RootScatterLDS<K> L;
-    if (P.ctl->error) return;
-    load_split(L.sp, P.gsplit);
+__global__ __launch_bounds__(NT) void k_lvl_scatter(Params P, uint32_t l) {
+    __shared__ LvlScatterLDS<K> L;
+    if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 1)) return;
+    const uint32_t seg = P.tile2seg[l][blockIdx.x];
+    const LvlSeg g = P.lseg[l][seg];
+    load_split(L.sp, &P.lsplit[l][seg]);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const uint32_t nb = uni(L.sp.nb), n = P.S.n;
-    for (uint32_t b = tid; b < NBPAD; b += NT) L.run[b] = b < nb ? P.totals[b] : 0u;
+    const uint32_t nb = uni(L.sp.nb);
+    const uint32_t *tot = &P.ltot[l][(size_t)seg * NBPAD];
+    for (uint32_t b = tid; b < NBPAD; b += NT) L.run[b] = b < nb ? tot[b] : 0u;
     __syncthreads();
     block_scan(L.run, (int)nb, L.tmp, true, AddOp(), 0u);
-    for (uint32_t b = tid; b < nb; b += NT) L.run[b] += P.hist[(size_t)blockIdx.x * NBPAD + b];
+    for (uint32_t b = tid; b < nb; b += NT) L.run[b] += g.begin + P.hist[(size_t)blockIdx.x * NBPAD + b];
     __syncthreads();
+    Rec *out = out_is_r1(g.meta) ? P.R1 : P.R0;
+    const uint32_t lt = blockIdx.x - g.tile0;
     for (uint32_t ch = 0; ch < ROOT_CHUNKS; ++ch) {
-        const uint32_t c0 = (blockIdx.x * ROOT_CHUNKS + ch) * (uint32_t)(NT * K);
-        if (c0 >= n) break;
+        const uint32_t c0 = (lt * ROOT_CHUNKS + ch) * (uint32_t)(NT * K);
+        if (c0 >= g.size) break;
         Rec r[K];
         uint32_t m[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-            if (e < n) {
-                r[j] = make_rec(P.S, e);
-                m[j] = P.bkt[e];
+            if (e < g.size) {
+                r[j] = seg_rec(P, g.meta, g.begin + e);
+                m[j] = P.bkt[g.begin + e];
             } else {
                 m[j] = nb;
             }
         }
-        scatter_chunk<K>(L.sc, L.tmp, L.sp, m, r, min((uint32_t)(NT * K), n - c0), L.run, P.R1, n, &P.ctl->error);
+        scatter_chunk<K>(L.sc, L.tmp, L.sp, m, r, min((uint32_t)(NT * K), g.size - c0), L.run, out, P.S.n,
+                         &P.ctl->error);
     }
 }
 
-// Children of the root step become the first tasks of the queue.
-__global__ __launch_bounds__(NT) void k_root_schedule(Params P, uint32_t depth) {
-    __shared__ Split sp;
-    __shared__ uint32_t bst[NBPAD];
-    __shared__ uint32_t fl[NBPAD];
-    __shared__ uint32_t tmp[NW];
-    if (P.ctl->error) return;
-    load_split(sp, P.gsplit);
-    const uint32_t nb = uni(sp.nb);
-    for (uint32_t b = threadIdx.x; b < NBPAD; b += NT) {
-        bst[b] = b < nb ? P.totals[b] : 0u;
-        fl[b] = (b < nb && P.totals[b]) ? 1u : 0u;
+struct LvlSchedLDS {
+    Split sp;
+    uint32_t bst[NBPAD];      // bucket starts (segment-relative)
+    uint32_t cnt[NBPAD];
+    uint32_t kind[NBPAD];     // 1 worker task, 2 small (base case)
+    uint32_t rk[NBPAD];       // worker task rank, later small-list position
+    uint32_t psz[NBPAD + 1];  // size prefix over the small list
+    uint16_t lsmall[NBPAD];
+    uint16_t cfirst[NBPAD + 1];
+    uint32_t nchunk;
+    unsigned long long pos, db;
+    uint32_t tmp[NW];
+};
+
+// Children of a level's segment: the next level's segments, worker tasks for
+// the other large buckets, identical strings finished here, and the small
+// buckets as base-case chunk tasks (group descriptors, chunks of at most
+// C - threshold strings, never splitting a group).
+__global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
+    __shared__ LvlSchedLDS L;
+    if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 0)) return;
+    const int tid = threadIdx.x;
+    const LvlSeg g = P.lseg[l][blockIdx.x];
+    load_split(L.sp, &P.lsplit[l][blockIdx.x]);
+    const uint32_t nb = uni(L.sp.nb), h = g.depth;
+    const uint32_t cpar = out_is_r1(g.meta) ? M_PARITY : 0u;
+    const Rec *out = out_is_r1(g.meta) ? P.R1 : P.R0;
+    const uint32_t *tot = &P.ltot[l][(size_t)blockIdx.x * NBPAD];
+    for (uint32_t b = tid; b < NBPAD; b += NT) {
+        const uint32_t c = b < nb ? tot[b] : 0u;
+        L.cnt[b] = c;
+        L.bst[b] = c;
+        uint32_t kind = 0;
+        if (c) {
+            const bool ident = (b & 1) && L.sp.zr[b >> 1];
+            if (ident) kind = 3;
+            else if (!(c > LVL_MIN && l + 1 < LMAX)) kind = c > P.tbase ? 1u : 2u;
+        }
+        L.kind[b] = kind;
+        L.rk[b] = kind == 1 ? 1u : 0u;
     }
     __syncthreads();
-    block_scan(bst, (int)nb, tmp, true, AddOp(), 0u);
-    const uint32_t k = block_scan(fl, (int)nb, tmp, true, AddOp(), 0u);
-    for (uint32_t b = threadIdx.x; b < nb; b += NT) {
-        const uint32_t cnt = P.totals[b];
-        if (!cnt) continue;
-        const uint32_t st = bst[b], l = b >> 1;
-        const bool odd = b & 1;
-        const uint32_t cd = odd ? depth + 8 : ((b == 0 || b == nb - 1) ? depth : depth + sp.hl[l]);
-        if (P.lcp && st > 0) P.lcp[st] = SEAM | depth;
-        Slot *s = &P.ring[fl[b]];
-        s->begin = st;
-        s->size = cnt;
-        s->depth = cd;
-        s->meta = M_PARITY | ((odd && sp.zr[l]) ? M_IDENT : 0u);
-        s->setbase = 0;
-        s->seq = (unsigned long long)fl[b] + 1;
+    block_scan(L.bst, (int)nb, L.tmp, true, AddOp(), 0u);
+    const uint32_t ntask = uni(block_scan(L.rk, (int)nb, L.tmp, true, AddOp(), 0u));
+    // seams and next-level segments
+    for (uint32_t b = tid; b < nb; b += NT) {
+        const uint32_t c = L.cnt[b], st = L.bst[b];
+        if (!c) continue;
+        if (P.lcp && st > 0) P.lcp[g.begin + st] = SEAM | h;
+        if (L.kind[b] == 0)
+            lvl_append(P, l + 1, LvlSeg{g.begin + st, c, child_depth(L.sp, h, b), cpar, 0, 0, g.setbase, 0});
     }
-    if (threadIdx.x == 0) {
-        P.ctl->tail = k;
-        P.ctl->pending = k;
+    // identical strings (an equality bucket whose splitter ends the string):
+    // already in input order, lcp = length
+    for (uint32_t b = 1; b < nb; b += 2) {
+        if (uni(L.kind[b]) != 3) continue;
+        const uint32_t c = L.cnt[b], st = g.begin + L.bst[b];
+        for (uint32_t i = tid; i < c; i += NT) {
+            const Rec r = out[st + i];
+            P.perm[st + i] = r.id - g.setbase;
+            if (P.lcp && i > 0) P.lcp[st + i] = r.ln;
+        }
+    }
+    // small list and chunks
+    for (uint32_t b = tid; b < NBPAD; b += NT) L.psz[b] = (b < nb && L.kind[b] == 2) ? 1u : 0u;
+    __syncthreads();
+    const uint32_t nsmall = uni(block_scan(L.psz, (int)nb, L.tmp, true, AddOp(), 0u));
+    for (uint32_t b = tid; b < nb; b += NT)
+        if (L.kind[b] == 2) L.lsmall[L.psz[b]] = (uint16_t)b;
+    __syncthreads();
+    for (uint32_t k = tid; k < nsmall; k += NT) L.psz[k] = L.cnt[L.lsmall[k]];
+    __syncthreads();
+    const uint32_t small_total = block_scan(L.psz, (int)nsmall, L.tmp, true, AddOp(), 0u);
+    if (tid == 0) {
+        L.psz[nsmall] = small_total;
+        L.nchunk = 0;
+    }
+    __syncthreads();
+    const uint32_t cap = (P.tbase * 2 <= P.chunk) ? P.chunk - P.tbase : 0u;
+    for (uint32_t k = tid; k < nsmall; k += NT) {
+        const uint32_t ck = cap ? L.psz[k] / cap : k;
+        const uint32_t cp = k ? (cap ? L.psz[k - 1] / cap : k - 1) : 0xFFFFFFFFu;
+        if (ck != cp) L.cfirst[ck] = (uint16_t)k;
+        if (k == nsmall - 1) L.nchunk = ck + 1;
+    }
+    __syncthreads();
+    const uint32_t nchunk = uni(L.nchunk);
+    if (tid == 0) {
+        L.cfirst[nchunk] = (uint16_t)nsmall;
+        const unsigned long long nt = (unsigned long long)ntask + nchunk;
+        if (nt) {
+            add_agent(&P.ctl->pending, nt);
+            L.pos = add_agent(&P.ctl->tail, nt);
+        }
+        L.db = nsmall ? add_agent(&P.ctl->desc_top, (unsigned long long)nsmall) : 0ull;
+        if (L.db + nsmall > P.desc_cap) atomicOr(&P.ctl->error, ERR_INTERNAL);
+    }
+    __syncthreads();
+    const unsigned long long pos = uni64(L.pos), db = uni64(L.db);
+    if (db + nsmall > P.desc_cap) return;
+    for (uint32_t b = tid; b < nb; b += NT)
+        if (L.kind[b] == 1)
+            seed_task(P, pos + L.rk[b],
+                      Task{g.begin + L.bst[b], L.cnt[b], child_depth(L.sp, h, b), cpar, g.setbase});
+    for (uint32_t k = tid; k < nsmall; k += NT) {
+        const uint32_t b = L.lsmall[k];
+        P.desc[db + k] = GroupDesc{g.begin + L.bst[b], L.cnt[b], child_depth(L.sp, h, b), 0u};
+    }
+    for (uint32_t c = tid; c < nchunk; c += NT) {
+        const uint32_t k0 = L.cfirst[c], k1 = L.cfirst[c + 1];
+        seed_task(P, pos + ntask + c,
+                  Task{(uint32_t)(db + k0), k1 - k0, L.psz[k1] - L.psz[k0], M_CHUNK | cpar, g.setbase});
     }
 }
 
@@ -1319,7 +1465,7 @@ __global__ void k_seam(Params P) {
 // Debug dump of one root step.
 __global__ void k_debug_dump(Params P, uint32_t depth, uint64_t *keys, uint64_t *split, uint64_t *tree,
                              uint32_t *info, uint16_t *bucket, uint32_t *hist, uint32_t *perm) {
-    const Split *sp = P.gsplit;
+    const Split *sp = &P.lsplit[0][0];
     const uint32_t n = P.S.n;
     for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
         const Rec r = make_rec(P.S, i);
@@ -1332,7 +1478,7 @@ __global__ void k_debug_dump(Params P, uint32_t depth, uint64_t *keys, uint64_t 
             split[j] = j < sp->v ? splitter(*sp, j) : 0;
             tree[j] = (j < sp->v) ? sp->tree[j + 1] : 0;
         }
-        for (uint32_t b = threadIdx.x; b < NBPAD; b += NT) hist[b] = b < sp->nb ? P.totals[b] : 0;
+        for (uint32_t b = threadIdx.x; b < NBPAD; b += NT) hist[b] = b < sp->nb ? P.ltot[0][b] : 0;
         if (threadIdx.x == 0) {
             info[0] = sp->v;
             info[1] = sp->d;
@@ -1371,9 +1517,9 @@ template __global__ void k_worker<4, 512>(Params);
 template __global__ void k_worker<4, 1024>(Params);
 template __global__ void k_worker<8, 512>(Params);
 template __global__ void k_worker<8, 1024>(Params);
-template __global__ void k_root_classify<4>(Params, uint32_t);
-template __global__ void k_root_classify<8>(Params, uint32_t);
-template __global__ void k_root_scatter<4>(Params);
-template __global__ void k_root_scatter<8>(Params);
+template __global__ void k_lvl_classify<4>(Params, uint32_t);
+template __global__ void k_lvl_classify<8>(Params, uint32_t);
+template __global__ void k_lvl_scatter<4>(Params, uint32_t);
+template __global__ void k_lvl_scatter<8>(Params, uint32_t);
 
 }  // namespace ssd

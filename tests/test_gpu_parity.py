@@ -216,3 +216,46 @@ def test_batched_small(sorter):
         rp, rh = oracle.sort(sub)
         assert np.array_equal(p[a:b], rp), s
         assert np.array_equal(h[a:b], rh), s
+
+
+def _level_one_strings(seed):
+    """60000 strings behind one 8-byte key (an equality bucket above the
+    second whole-GPU level's threshold), 50000 in a range, some duplicates."""
+    rng = np.random.default_rng(seed)
+    strs = [b"commonpr" + bytes(rng.integers(97, 105, size=int(rng.integers(1, 13))).astype(np.uint8))
+            for _ in range(60000)]
+    strs += [b"zz" + bytes(rng.integers(97, 101, size=int(rng.integers(1, 13))).astype(np.uint8))
+             for _ in range(50000)]
+    for _ in range(3000):
+        strs[int(rng.integers(0, 110000))] = strs[int(rng.integers(0, 110000))]
+    return strs
+
+
+def test_second_level(sorter):
+    assert_parity(sorter, W.from_list(_level_one_strings(50)), "second whole-GPU level")
+
+
+def test_batched_large_sets(sorter):
+    """Sets above the whole-GPU threshold go through the levels, the others
+    straight to the workers; every set equals its own oracle sort."""
+    from paper_1403_2056_amd import ssort
+    strs = _level_one_strings(51)
+    rng = np.random.default_rng(52)
+    sets = [strs[:80000]]
+    for _ in range(5):
+        sets.append([bytes(rng.integers(97, 100, size=int(rng.integers(0, 11))).astype(np.uint8))
+                     for _ in range(int(rng.integers(0, 300)))])
+    sets.append(strs[30000:100000])
+    flat = [x for st in sets for x in st]
+    sb = np.cumsum([0] + [len(st) for st in sets]).astype(np.uint32)
+    ss = W.from_list(flat)
+    d = ssort.strings_to_device(ss)
+    perm, lcp = sorter.sort_batched(d, torch.from_numpy(sb.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    assert sorter.query_error() == 0
+    p, h = ssort.to_numpy_u32(perm), ssort.to_numpy_u32(lcp)
+    for k, st in enumerate(sets):
+        a, b = int(sb[k]), int(sb[k + 1])
+        rp, rh = oracle.sort(W.from_list(st))
+        assert np.array_equal(p[a:b], rp), k
+        assert np.array_equal(h[a:b], rh), k
