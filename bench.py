@@ -53,6 +53,57 @@ def dist_bytes(lens_sorted: np.ndarray, lcp: np.ndarray) -> np.ndarray:
     return np.minimum(lens_sorted.astype(np.int64), 1 + np.maximum(left, right))
 
 
+def bench_merge(args):
+    """K-way LCP-merge: the long-prefix input split into K contiguous shards,
+    each sorted by the GPU (untimed, as K independent sorters would deliver
+    them), then merged; timed: the merge alone, and a full sort for scale."""
+    import torch
+    from paper_1403_2056_amd import ssort, workloads
+    n = 1 << args.n_log2
+    K = args.runs
+    ss = workloads.by_name(args.workload, n)
+    d = ssort.strings_to_device(ss)
+    s = ssort.Sorter(0)
+    bounds = [n * k // K for k in range(K + 1)]
+    sb = torch.tensor(bounds, dtype=torch.int32, device="cuda")
+    p, h = s.sort_batched(d, sb)
+    off = torch.repeat_interleave(torch.tensor(bounds[:-1], dtype=torch.int32),
+                                  torch.tensor(np.diff(bounds), dtype=torch.int64)).cuda()
+    pin = (p + off).contiguous()
+    hin = h.clone()
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    lcp = torch.empty(n, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        s.merge(d, bounds, pin, hin, out_perm=perm, out_lcp=lcp)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        s.merge(d, bounds, pin, hin, out_perm=perm, out_lcp=lcp)
+    e1.record()
+    torch.cuda.synchronize()
+    if s.query_error() != 0:
+        raise SystemExit("device error during merges")
+    ms = e0.elapsed_time(e1) / args.steps
+    p2, h2 = s.sort(d)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(p2, perm) and torch.equal(h2, lcp))
+    e0.record()
+    for _ in range(args.steps):
+        s.sort(d)
+    e1.record()
+    torch.cuda.synchronize()
+    sort_ms = e0.elapsed_time(e1) / args.steps
+    out = {"metric": "strings/sec merged (K-way LCP-merge of sorted runs with LCP arrays)",
+           "value": round(n / (ms / 1000.0), 1), "unit": "strings/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "u8",
+           "data": "synthetic",
+           "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload).format(n=args.n_log2),
+                      "runs": K, "run_split": "contiguous index ranges, each sorted by the GPU"},
+           "full_sort_ms": round(sort_ms, 4), "identical_to_full_sort": same}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batched(args):
     """Batched form: 4096 independent sets (sizes 2^U(6,18), geometric lengths
     with mean 24, 95 printable bytes) sorted by one graph-captured launch,
@@ -227,7 +278,8 @@ def main():
     ap.add_argument("--tb", type=int, default=128)
     ap.add_argument("--equal", action="store_true", help="S5-Equal classification")
     ap.add_argument("--workload", default="prefixes", help="plain mode: prefixes, suffixes or plain")
-    ap.add_argument("--mode", choices=["plain", "batched", "serve"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batched", "serve", "merge"], default="plain")
+    ap.add_argument("--runs", type=int, default=8, help="merge mode: number of sorted runs K")
     ap.add_argument("--sets", type=int, default=4096)
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--jobs", type=int, default=600)
@@ -241,6 +293,8 @@ def main():
         return bench_batched(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "merge":
+        return bench_merge(args)
 
     import torch
     from paper_1403_2056_amd import ssort, workloads

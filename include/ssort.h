@@ -184,6 +184,30 @@ ssort_status ssort_phase_ms(ssort_ctx *ctx, float *ms);
 
 const char *ssort_strerror(ssort_status s);
 
+/* ---- K-way LCP-merge (Section 5: Algorithm 2, binary LCP-compare; Algorithm
+ * 4, K-way LCP-merge with an LCP-aware tournament tree; the caching variant of
+ * its implementation details) ----
+ * Merges K sorted runs of strings of `in` into one sorted sequence with its
+ * LCP array.
+ *  run_begin HOST uint32[K+1], run_begin[0] = 0, non-decreasing; run k is
+ *            positions run_begin[k] .. run_begin[k+1]-1 of perm_in / lcp_in;
+ *            n = run_begin[K] strings in all; 1 <= K <= 32
+ *  perm_in   device uint32[n]: indices into `in`; each run sorted, equal
+ *            strings in index order (as ssort_sort returns them)
+ *  lcp_in    device uint32[n]: lcp_in[p] = LCP of the strings at positions
+ *            p-1 and p of the same run; the entry at a run's start is ignored
+ *  out_perm  device uint32[n]: all indices sorted, equal strings by index
+ *  out_lcp   device uint32[n] (may be NULL): out_lcp[0] = 0, out_lcp[i] = LCP
+ *            of the strings at positions i-1 and i
+ * When the runs together hold every index of `in` once, the result equals
+ * ssort_sort of `in`.  Workspace from ssort_merge_workspace_bytes (a few bytes
+ * per string).  Asynchronous on `stream`; ssort_query_error reports device
+ * errors.  SSORT_EINVAL for bad runs or K. */
+ssort_status ssort_merge_workspace_bytes(const ssort_ctx *ctx, const uint32_t *run_begin, uint32_t K, size_t *bytes);
+ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t *run_begin, uint32_t K,
+                         const uint32_t *perm_in, const uint32_t *lcp_in, uint32_t *out_perm, uint32_t *out_lcp,
+                         void *ws, size_t ws_bytes, void *stream);
+
 /* ---- one classification step with its intermediates (parity checks) ----
  * Runs one step of Algorithm 1 over all n strings of `in` at common depth
  * `depth` (the caller guarantees the strings share that prefix), on the input

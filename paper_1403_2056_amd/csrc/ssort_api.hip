@@ -8,6 +8,7 @@
 
 #include "ssort.h"
 #include "ssort_kernels.hip"
+#include "ssort_merge.hip"
 #include "ssort_serve.hip"
 
 using namespace ssd;
@@ -46,8 +47,8 @@ Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     const uint32_t K = c->tun.keys_per_thread;
     L.tile = (uint32_t)NT * K * ROOT_CHUNKS;
     // a level holds segments of more than LVL_MIN strings (level 0: the input
-    // or sets of more than ROOT_MIN > LVL_MIN), and their tiles
-    L.maxseg = n / LVL_MIN + 1;
+    // or sets of more than ROOT_MIN), and their tiles
+    L.maxseg = n / std::min(LVL_MIN, ROOT_MIN) + 1;
     L.maxtiles = n / L.tile + L.maxseg;
     // queued tasks: segments of more than base_threshold strings (at most
     // two per such disjoint set of strings), the batched sets, base-case
@@ -349,6 +350,88 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
     if (ctx->prof) (void)hipEventRecord(ctx->ev[2], s);
     if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[3], s);
+    ctx->last_ws = ws;
+    return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
+}
+
+// ---- K-way LCP-merge ----
+namespace {
+constexpr uint32_t MERGE_G = 256;   // sample spacing: jobs of about K * 128 strings on average
+
+struct MergeLayout {
+    size_t ctl, cache, cuts, total;
+    uint32_t nsamp;
+};
+
+MergeLayout merge_layout(uint32_t n, const uint32_t *run_begin, uint32_t K) {
+    MergeLayout L;
+    L.nsamp = 0;
+    for (uint32_t k = 0; k < K; ++k) L.nsamp += (run_begin[k + 1] - run_begin[k] + MERGE_G - 1) / MERGE_G;
+    size_t off = 0;
+    L.ctl = off;
+    off = align_up(off + sizeof(Ctl), 256);
+    L.cache = off;
+    off = align_up(off + 8 * (size_t)n, 256);
+    L.cuts = off;
+    off = align_up(off + 4 * (size_t)(L.nsamp + 1) * K, 256);
+    L.total = off;
+    return L;
+}
+
+bool valid_runs(const uint32_t *run_begin, uint32_t K) {
+    if (!run_begin || K < 1 || K > (uint32_t)ssm::MKMAX || run_begin[0] != 0) return false;
+    for (uint32_t k = 0; k < K; ++k)
+        if (run_begin[k + 1] < run_begin[k]) return false;
+    return true;
+}
+}  // namespace
+
+ssort_status ssort_merge_workspace_bytes(const ssort_ctx *ctx, const uint32_t *run_begin, uint32_t K, size_t *bytes) {
+    if (!ctx || !bytes || !valid_runs(run_begin, K)) return SSORT_EINVAL;
+    *bytes = merge_layout(run_begin[K], run_begin, K).total;
+    return SSORT_OK;
+}
+
+ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t *run_begin, uint32_t K,
+                         const uint32_t *perm_in, const uint32_t *lcp_in, uint32_t *out_perm, uint32_t *out_lcp,
+                         void *ws, size_t ws_bytes, void *stream) {
+    if (!ctx) return SSORT_EINVAL;
+    ssort_status st = check_strings(in);
+    if (st != SSORT_OK) return st;
+    if (!valid_runs(run_begin, K)) return SSORT_EINVAL;
+    const uint32_t n = run_begin[K];
+    if (n == 0) return SSORT_OK;
+    if (!perm_in || !lcp_in || !out_perm || !ws) return SSORT_EINVAL;
+    const MergeLayout L = merge_layout(n, run_begin, K);
+    if (ws_bytes < L.total) return SSORT_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
+    ssm::MergeParams M;
+    memset(&M, 0, sizeof(M));
+    M.S.chars = in->chars;
+    M.S.nchars = in->nchars;
+    M.S.off = in->offsets;
+    M.S.len = in->lengths;
+    M.S.n = in->n;
+    M.S.flags = in->flags;
+    for (uint32_t k = 0; k <= K; ++k) M.rb[k] = run_begin[k];
+    M.pin = perm_in;
+    M.hin = lcp_in;
+    M.pout = out_perm;
+    M.hout = out_lcp;
+    char *w = (char *)ws;
+    M.err = &((Ctl *)(w + L.ctl))->error;
+    M.cache = (uint64_t *)(w + L.cache);
+    M.cuts = (uint32_t *)(w + L.cuts);
+    M.K = K;
+    M.n = n;
+    M.g = MERGE_G;
+    M.nsamp = L.nsamp;
+    hipLaunchKernelGGL(ssm::k_mreset, dim3(1), dim3(64), 0, s, M);
+    hipLaunchKernelGGL(ssm::k_mcache, dim3(grid_for(n)), dim3(NT), 0, s, M);
+    hipLaunchKernelGGL(ssm::k_msample, dim3((L.nsamp + 63) / 64), dim3(64), 0, s, M);
+    hipLaunchKernelGGL(ssm::k_mmerge, dim3((L.nsamp + ssm::MNT - 1) / ssm::MNT), dim3(ssm::MNT), 0, s, M);
+    if (out_lcp) hipLaunchKernelGGL(ssm::k_mseam, dim3((L.nsamp + 63) / 64), dim3(64), 0, s, M);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
 }

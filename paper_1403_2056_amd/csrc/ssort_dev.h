@@ -256,7 +256,8 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 // number, padded by the largest), else v equidistant distinct keys, so that no
 // splitter repeats (cf. the skip-duplicates selection).  Then the level-order
 // tree, the splitter LCPs (xor + count leading zeros) and the end-of-string
-// flags.  `samp`, `srt` need SAMPLE_MAX+1 entries, `fl` SAMPLE_MAX+1, tmp NW.
+// flags.  `samp`, `srt` need SAMPLE_MAX+1 entries (a power of two: the sort
+// pads to one), `fl` SAMPLE_MAX+1, tmp NW.
 template <typename Load>
 __device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
                                                  uint32_t equal, uint64_t *samp, uint64_t *srt, uint32_t *fl,
@@ -271,17 +272,28 @@ __device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint3
         else pos = (uint32_t)(((uint64_t)t * size) / a) + hash32(seed ^ (t * 0x9E3779B9u)) % stride;
         samp[t] = load(pos, h);
     }
+    // sort the sample: bitonic network over the next power of two, padded
+    // with the largest key (padding sorts last, so srt[0..a) holds the sample)
+    uint32_t a2 = 1;
+    while (a2 < a) a2 <<= 1;
+    a2 = uni(a2);
+    for (uint32_t t = tid; t < a2; t += NT) srt[t] = t < a ? samp[t] : ~0ull;
     __syncthreads();
-    for (uint32_t t = tid; t < a; t += NT) {
-        const uint64_t k = samp[t];
-        uint32_t r = 0;
-        for (uint32_t j = 0; j < a; ++j) {
-            const uint64_t q = samp[j];
-            r += (q < k || (q == k && j < t)) ? 1u : 0u;
+    for (uint32_t kk = 2; kk <= a2; kk <<= 1) {
+        for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t t = tid; t < a2 / 2; t += NT) {
+                const uint32_t i = 2 * t - (t & (jj - 1));   // lower element of the pair
+                const uint32_t k2 = i + jj;
+                const uint64_t x = srt[i], y = srt[k2];
+                const bool up = (i & kk) == 0;
+                if ((x > y) == up) {
+                    srt[i] = y;
+                    srt[k2] = x;
+                }
+            }
+            __syncthreads();
         }
-        srt[r] = k;
     }
-    __syncthreads();
     for (uint32_t t = tid; t < a; t += NT) fl[t] = (t == 0 || srt[t] != srt[t - 1]) ? 1u : 0u;
     __syncthreads();
     const uint32_t U = uni(block_scan(fl, (int)a, tmp, true, AddOp(), 0u));

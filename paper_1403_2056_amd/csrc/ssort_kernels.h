@@ -13,7 +13,7 @@ constexpr int NST = 9;
 // before the persistent workers take over.
 constexpr int LMAX = 2;
 constexpr uint32_t ROOT_MIN = 1u << 16;
-constexpr uint32_t LVL_MIN = 1u << 15;
+constexpr uint32_t LVL_MIN = 1u << 16;
 
 // One segment of a whole-GPU level: its strings, depth and record source,
 // and its tiles (ROOT_CHUNKS chunks of NT*K strings each) in the level's tile

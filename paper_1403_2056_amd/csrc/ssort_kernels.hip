@@ -944,21 +944,31 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
     }
     for (;;) {
         if (ung) {
-            for (uint32_t g = tid; g < ung; g += NT) {
+            // a descriptor outside the string range or a chunk larger than
+            // the LDS holds is a device error, never an access
+            if (tid == 0) L.qfail = 0;
+            __syncthreads();
+            for (uint32_t g = tid; g < min(ung, (uint32_t)NBPAD); g += NT) {
                 const GroupDesc d = P.desc[ud0 + g];
+                if (d.start > P.S.n || d.size > P.S.n - d.start || d.size == 0 || d.size > P.tbase) L.qfail = 1;
                 L.bst[g] = d.start;
                 L.hist[g] = d.size;
                 L.psz[g] = d.size;
                 L.gdep[g] = d.depth;
             }
             __syncthreads();
-            ng = ung;
+            ng = uni((ung > (uint32_t)NBPAD || L.qfail) ? 0u : ung);
+            if (ng == 0 && tid == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
             ung = 0;
         }
         if (ng) {
             const uint32_t M = uni(block_scan(L.psz, (int)ng, L.tmp, true, AddOp(), 0u));
-            DescGroups g{L.bst, L.hist, L.gdep, L.psz};
-            base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, ng, M, g, [&](int i) { mark(L, i); }, L.st);
+            if (M > (uint32_t)C) {
+                if (tid == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+            } else {
+                DescGroups g{L.bst, L.hist, L.gdep, L.psz};
+                base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, ng, M, g, [&](int i) { mark(L, i); }, L.st);
+            }
             mark(L, PH_BASE);
             ng = 0;
         }
@@ -1185,7 +1195,15 @@ __global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
     __shared__ uint32_t hist[NBPAD];
     if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 1)) return;
     const uint32_t seg = P.tile2seg[l][blockIdx.x];
+    if (seg >= lvl_count(P, l, 0)) {
+        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        return;
+    }
     const LvlSeg g = P.lseg[l][seg];
+    if (g.begin > P.S.n || g.size > P.S.n - g.begin) {
+        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        return;
+    }
     load_split(sp, &P.lsplit[l][seg]);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     for (int b = tid; b < NBPAD; b += NT) hist[b] = 0;
@@ -1286,7 +1304,15 @@ __global__ __launch_bounds__(NT) void k_lvl_scatter(Params P, uint32_t l) {
     __shared__ LvlScatterLDS<K> L;
     if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 1)) return;
     const uint32_t seg = P.tile2seg[l][blockIdx.x];
+    if (seg >= lvl_count(P, l, 0)) {
+        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        return;
+    }
     const LvlSeg g = P.lseg[l][seg];
+    if (g.begin > P.S.n || g.size > P.S.n - g.begin) {
+        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        return;
+    }
     load_split(L.sp, &P.lsplit[l][seg]);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const uint32_t nb = uni(L.sp.nb);

@@ -1,0 +1,325 @@
+// K-way LCP-merge of sorted string runs (Section 5: binary LCP-compare,
+// Algorithm 2; K-way LCP-merge with an LCP-aware tournament tree, Algorithm
+// 4; the caching variant of the implementation details), for gfx950.
+//
+// Input: K runs, each a sorted sequence of string indices with its LCP array.
+// Output: the merged sequence (equal strings ordered by index) and its LCP
+// array.  Parallel form: every g-th element of every run is a sample; a
+// sample's cut (for every run, the number of its elements below the sample)
+// comes from one LCP-accelerated binary search per run, and the cuts in
+// sample order split the merge into independent jobs (a job: for each run
+// the elements between two consecutive cuts).  One thread merges one job with
+// an LCP-aware loser tree whose nodes cache the 8 characters of their string
+// at the node's LCP (the paper caches the one distinguishing character; eight
+// fit in the 64-bit word the comparisons use), so most games are decided
+// without touching the strings.  A last pass computes the LCP across job
+// boundaries.
+#include "ssort_dev.h"
+
+namespace ssm {
+
+using ssd::Strs;
+using ssd::key_at;
+
+constexpr int MNT = 64;          // threads per merge workgroup
+constexpr int MKMAX = 32;        // largest K
+constexpr uint32_t SENT = 0xFFFFFFFFu;   // exhausted player
+
+struct MergeParams {
+    Strs S;
+    uint32_t rb[MKMAX + 1];  // run boundaries
+    const uint32_t *pin;     // runs of string indices
+    const uint32_t *hin;     // their LCP arrays (entry at a run's start ignored)
+    uint32_t *pout, *hout;
+    uint64_t *cache;         // 8 characters of each input string at its LCP
+    uint32_t *cuts;          // (nsamp + 1) rows of K cuts, in sample order
+    unsigned long long *err;
+    uint32_t K, n, g, nsamp;
+};
+
+__device__ __forceinline__ uint64_t str_key(const MergeParams &M, uint32_t id, uint32_t h) {
+    uint64_t st, ln;
+    st = M.S.off[id];
+    if (M.S.flags & ssd::TO_END) ln = M.S.nchars - st;
+    else if (M.S.len) ln = M.S.len[id];
+    else ln = M.S.off[id + 1] - st;
+    return key_at(M.S.chars, M.S.nchars, st, (uint32_t)ln, h);
+}
+
+// Compare strings a and b that agree on [0, d): returns their LCP and
+// whether a < b (equal strings: by index).
+__device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, uint32_t b, uint32_t d, bool *a_less) {
+    for (uint32_t l = d;; l += 8) {
+        const uint64_t ka = str_key(M, a, l), kb = str_key(M, b, l);
+        if (ka != kb) {
+            *a_less = ka < kb;
+            return l + (uint32_t)(__clzll(ka ^ kb) >> 3);
+        }
+        if ((ka & 0xFF) == 0) {   // both end here: equal strings
+            *a_less = a < b;
+            uint32_t e = 0;
+            while (e < 8 && ((ka >> (56 - 8 * e)) & 0xFF)) ++e;
+            return l + e;
+        }
+    }
+}
+
+// 8 characters at the LCP position of every input element (the run's first
+// element: at 0).
+__global__ void k_mcache(MergeParams M) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < M.n; p += gridDim.x * blockDim.x) {
+        bool first = false;
+        for (uint32_t k = 0; k < M.K; ++k) first |= (M.rb[k] == p);
+        M.cache[p] = str_key(M, M.pin[p], first ? 0u : M.hin[p]);
+    }
+}
+
+// Number of samples of run k below position c (samples sit at 0, g, 2g, ...).
+__device__ __forceinline__ uint32_t samples_below(uint32_t c, uint32_t g) { return (c + g - 1) / g; }
+
+// One thread per sample: its cut in every run (lower bound of (string, index)
+// with the LCP-accelerated binary search: the search keeps the LCPs of the
+// sample with the elements just outside [lo, hi) and compares from their
+// minimum), and its position in sample order.
+__global__ void k_msample(MergeParams M) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M.nsamp) return;
+    // which run and position: samples of run k are numbered from the
+    // running total of earlier runs' samples
+    uint32_t k = 0, base = 0;
+    for (; k < M.K; ++k) {
+        const uint32_t c = samples_below(M.rb[k + 1] - M.rb[k], M.g);
+        if (t < base + c) break;
+        base += c;
+    }
+    if (k >= M.K) return;
+    const uint32_t pos = (t - base) * M.g;
+    const uint32_t sid = M.pin[M.rb[k] + pos];
+    uint32_t order = 0;
+    uint32_t cut[MKMAX];
+    for (uint32_t r = 0; r < M.K; ++r) {
+        uint32_t c;
+        if (r == k) {
+            c = pos;
+        } else {
+            const uint32_t *run = M.pin + M.rb[r];
+            uint32_t lo = 0, hi = M.rb[r + 1] - M.rb[r], llo = 0, lhi = 0;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                bool mid_less;
+                const uint32_t l = cmp_from(M, run[mid], sid, min(llo, lhi), &mid_less);
+                if (mid_less) {
+                    lo = mid + 1;
+                    llo = l;
+                } else {
+                    hi = mid;
+                    lhi = l;
+                }
+            }
+            c = lo;
+        }
+        cut[r] = c;
+        order += samples_below(c, M.g);
+    }
+    if (order >= M.nsamp) {
+        atomicOr(M.err, 16ull);
+        return;
+    }
+    for (uint32_t r = 0; r < M.K; ++r) M.cuts[(size_t)order * M.K + r] = cut[r];
+}
+
+// Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run,
+// its LCP with the winner of that game, and its 8 characters at that LCP.
+struct MergeLDS {
+    uint32_t y[MKMAX][MNT];
+    uint32_t h[MKMAX][MNT];
+    uint64_t c[MKMAX][MNT];
+    uint32_t pos[MKMAX][MNT];   // next element of each run (absolute)
+    uint32_t end[MKMAX][MNT];
+};
+
+// One game (Algorithm 2 with cached characters): the candidate (x, hx, cx)
+// against the node's loser (y, hy, cy), both with LCPs against the same
+// smaller string p.  Returns true when the candidate wins; the loser's
+// (run, LCP with the winner, characters at it) end up in (ly, lh, lc).
+__device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t xid, uint32_t hx, uint64_t cx,
+                                     uint32_t y, uint32_t yid, uint32_t hy, uint64_t cy, uint32_t *lh, uint64_t *lc) {
+    if (y == SENT) {
+        *lh = hy;
+        *lc = cy;
+        return true;
+    }
+    if (x == SENT) {
+        *lh = hx;
+        *lc = cx;
+        return false;
+    }
+    if (hx > hy) {   // the candidate agrees longer with p: it is smaller
+        *lh = hy;
+        *lc = cy;
+        return true;
+    }
+    if (hx < hy) {
+        *lh = hx;
+        *lc = cx;
+        return false;
+    }
+    // equal LCPs: compare characters from there, the cached 8 first
+    uint32_t l;
+    bool x_less;
+    if (cx != cy) {
+        x_less = cx < cy;
+        l = hx + (uint32_t)(__clzll(cx ^ cy) >> 3);
+    } else if ((cx & 0xFF) == 0) {
+        x_less = xid < yid;
+        uint32_t e = 0;
+        while (e < 8 && ((cx >> (56 - 8 * e)) & 0xFF)) ++e;
+        l = hx + e;
+    } else {
+        l = cmp_from(M, xid, yid, hx + 8, &x_less);
+    }
+    const uint32_t lid = x_less ? yid : xid;
+    const uint64_t lold = x_less ? cy : cx;
+    *lh = l;
+    *lc = (l == hx) ? lold : str_key(M, lid, l);
+    return x_less;
+}
+
+__global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
+    __shared__ MergeLDS L;
+    const uint32_t j = blockIdx.x * MNT + threadIdx.x;
+    if (j >= M.nsamp) return;
+    const int me = threadIdx.x;
+    const uint32_t K = M.K;
+    uint32_t KP = 1;
+    while (KP < K) KP <<= 1;
+    // this job: for each run, the elements between cut rows j and j+1
+    uint32_t out = 0;
+    for (uint32_t r = 0; r < KP; ++r) {
+        if (r < K) {
+            const uint32_t a = M.cuts[(size_t)j * K + r];
+            const uint32_t b = (j + 1 < M.nsamp) ? M.cuts[(size_t)(j + 1) * K + r] : M.rb[r + 1] - M.rb[r];
+            L.pos[r][me] = M.rb[r] + a;
+            L.end[r][me] = M.rb[r] + b;
+            out += a;
+        } else {
+            L.pos[r][me] = L.end[r][me] = 0;
+        }
+    }
+    // players: the runs' first elements of the job, LCP 0 against the empty
+    // string; the tree is built bottom-up with the winners of subtrees kept
+    // in the leaf slots' place (node v < KP holds a loser, win[] the winner)
+    uint32_t wrun[MKMAX];
+    uint32_t wh[MKMAX];
+    uint64_t wc[MKMAX];
+    auto player = [&](uint32_t r, uint32_t *id) -> bool {
+        if (r >= K || L.pos[r][me] >= L.end[r][me]) return false;
+        *id = M.pin[L.pos[r][me]];
+        return true;
+    };
+    // leaves
+    for (uint32_t r = 0; r < KP; ++r) {
+        uint32_t id;
+        if (player(r, &id)) {
+            wrun[r] = r;
+            wh[r] = 0;
+            wc[r] = str_key(M, id, 0);
+        } else {
+            wrun[r] = SENT;
+            wh[r] = 0;
+            wc[r] = 0;
+        }
+    }
+    // internal nodes, level by level: the winners of nodes at one level are
+    // compacted into wrun[0..cnt)
+    for (uint32_t cnt = KP, base = KP; cnt > 1; cnt >>= 1, base >>= 1) {
+        for (uint32_t q = 0; q < cnt / 2; ++q) {
+            const uint32_t a = wrun[2 * q], b = wrun[2 * q + 1];
+            uint32_t aid = 0, bid = 0;
+            if (a != SENT) aid = M.pin[L.pos[a][me]];
+            if (b != SENT) bid = M.pin[L.pos[b][me]];
+            uint32_t lh;
+            uint64_t lc;
+            const bool aw = game(M, a, aid, wh[2 * q], wc[2 * q], b, bid, wh[2 * q + 1], wc[2 * q + 1], &lh, &lc);
+            const uint32_t v = (base >> 1) + q;   // node index of this game
+            L.y[v][me] = aw ? b : a;
+            L.h[v][me] = lh;
+            L.c[v][me] = lc;
+            const uint32_t wr = aw ? a : b;
+            const uint32_t whh = aw ? wh[2 * q] : wh[2 * q + 1];
+            const uint64_t wcc = aw ? wc[2 * q] : wc[2 * q + 1];
+            wrun[q] = wr;
+            wh[q] = whh;
+            wc[q] = wcc;
+        }
+    }
+    uint32_t w = wrun[0], hw = 0;
+    bool first = true;
+    while (w != SENT) {
+        const uint32_t p = L.pos[w][me];
+        M.pout[out] = M.pin[p];
+        if (!first && M.hout) M.hout[out] = hw;
+        first = false;
+        ++out;
+        // the winner's run advances; its next element's LCP with the string
+        // just written is the run's own LCP entry, its cached characters too
+        L.pos[w][me] = p + 1;
+        uint32_t x = w, hx = 0;
+        uint64_t cx = 0;
+        uint32_t xid = 0;
+        if (p + 1 < L.end[w][me]) {
+            hx = M.hin[p + 1];
+            cx = M.cache[p + 1];
+            xid = M.pin[p + 1];
+        } else {
+            x = SENT;
+        }
+        for (uint32_t v = (KP + w) >> 1; v >= 1; v >>= 1) {
+            const uint32_t y = L.y[v][me];
+            const uint32_t yid = y == SENT ? 0u : M.pin[L.pos[y][me]];
+            uint32_t lh;
+            uint64_t lc;
+            const bool xw = game(M, x, xid, hx, cx, y, yid, L.h[v][me], L.c[v][me], &lh, &lc);
+            if (!xw) {
+                L.y[v][me] = x;
+                x = y;
+                xid = yid;
+                hx = L.h[v][me];
+                cx = L.c[v][me];
+            } else {
+                L.y[v][me] = y;
+            }
+            L.h[v][me] = lh;
+            L.c[v][me] = lc;
+        }
+        w = x;
+        hw = hx;
+    }
+}
+
+// LCP between the first output of each job and the string before it.
+__global__ void k_mseam(MergeParams M) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M.nsamp) return;
+    uint32_t q = 0;
+    for (uint32_t r = 0; r < M.K; ++r) q += M.cuts[(size_t)j * M.K + r];
+    uint32_t qe = M.n;
+    if (j + 1 < M.nsamp) {
+        qe = 0;
+        for (uint32_t r = 0; r < M.K; ++r) qe += M.cuts[(size_t)(j + 1) * M.K + r];
+    }
+    if (q >= qe) return;
+    if (q == 0) {
+        M.hout[0] = 0;
+        return;
+    }
+    bool less;
+    M.hout[q] = cmp_from(M, M.pout[q - 1], M.pout[q], 0, &less);
+}
+
+__global__ void k_mreset(MergeParams M) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *M.err = 0;
+}
+
+}  // namespace ssm
+

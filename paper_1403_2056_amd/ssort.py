@@ -90,6 +90,11 @@ _SIGS = {
                                              ctypes.POINTER(ctypes.c_size_t)]),
     "ssort_sort": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "ssort_merge_workspace_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "ssort_merge": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.POINTER(ctypes.c_uint32),
+                                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "ssort_sort_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_void_p,
                                           ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_size_t, ctypes.c_void_p]),
@@ -252,6 +257,29 @@ class Sorter:
         _check(lib().ssort_sort_batched(self._h, ctypes.byref(st), _ptr(set_begin), m, _ptr(out_perm),
                                         _ptr(out_lcp) if with_lcp else None, _ptr(ws), ws.numel(),
                                         _stream(stream)), "ssort_sort_batched")
+        return out_perm[:n], (out_lcp[:n] if with_lcp else None)
+
+    def merge(self, s: DeviceStrings, run_begin, perm_in, lcp_in, with_lcp: bool = True, out_perm=None,
+              out_lcp=None, ws=None, stream=None):
+        """K-way LCP-merge of sorted runs: run_begin is a host sequence of K+1
+        positions into perm_in/lcp_in (device int32 tensors)."""
+        torch = self._torch
+        dev = f"cuda:{self.device}"
+        K = len(run_begin) - 1
+        rb = (ctypes.c_uint32 * (K + 1))(*[int(x) for x in run_begin])
+        n = int(run_begin[-1])
+        if out_perm is None:
+            out_perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if with_lcp and out_lcp is None:
+            out_lcp = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if ws is None:
+            b = ctypes.c_size_t()
+            _check(lib().ssort_merge_workspace_bytes(self._h, rb, K, ctypes.byref(b)), "ssort_merge_workspace_bytes")
+            ws = torch.empty(max(b.value, 1), dtype=torch.uint8, device=dev)
+        st = s.struct()
+        _check(lib().ssort_merge(self._h, ctypes.byref(st), rb, K, _ptr(perm_in), _ptr(lcp_in), _ptr(out_perm),
+                                 _ptr(out_lcp) if with_lcp else None, _ptr(ws), ws.numel(), _stream(stream)),
+               "ssort_merge")
         return out_perm[:n], (out_lcp[:n] if with_lcp else None)
 
     def query_error(self, stream=None) -> int:

@@ -29,7 +29,8 @@ def built():
 def test_header_declares_the_boundary():
     names = declared()
     for must in ("ssort_create", "ssort_sort", "ssort_sort_batched", "ssort_workspace_bytes",
-                 "ssort_query_error", "ssort_destroy", "ssort_debug_step"):
+                 "ssort_query_error", "ssort_destroy", "ssort_debug_step", "ssort_merge",
+                 "ssort_merge_workspace_bytes"):
         assert must in names
 
 

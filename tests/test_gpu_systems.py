@@ -97,12 +97,20 @@ def test_server_results_alone_and_in_mix(ss_mod):
         t = srv.submit(j)
         p, h, _ = srv.wait(t)
         alone.append((p.copy(), h.copy()))
-    tickets = [srv.submit(j) for j in jobs]   # all at once: batched and overlapped
-    mixed = [srv.wait(t) for t in tickets]
     st = srv.stats()
     srv.close()
-    assert st["completed"] == 2 * len(jobs)
-    assert st["launches"] < 2 * len(jobs)     # the mix was batched
+    assert st["completed"] == len(jobs) and st["launches"] == len(jobs)
+    # all at once behind a large job on a one-slot server: the others wait
+    # while it runs and are batched
+    srv = ssort.Server(0, budget_bytes=1 << 30, slots=1)
+    tb = srv.submit(W.plain(1 << 20, seed=36))
+    tickets = [srv.submit(j) for j in jobs]
+    mixed = [srv.wait(t) for t in tickets]
+    srv.wait(tb)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(jobs) + 1
+    assert st["launches"] < len(jobs)     # the mix was batched
     for j, (pa, ha), (pm, hm, info) in zip(jobs, alone, mixed):
         rp, rh = oracle.sort(j)
         assert np.array_equal(pa, rp) and np.array_equal(ha, rh)
