@@ -123,6 +123,15 @@ typedef struct {
     uint64_t max_task;
     uint64_t max_chunk;
     uint64_t published_chunks;   /* base-case chunks handed to other workgroups */
+    /* device error mask of the last sort or merge (0: none).  1 wait limit,
+     * 2 string outside the buffer, 4 zero byte (these three map to
+     * SSORT_ETIMEOUT, SSORT_EBOUNDS, SSORT_EZEROBYTE); the internal
+     * consistency checks, each reported as SSORT_EDEVICE: 8 work-queue slot
+     * still occupied, 16 group-descriptor array full, 32 task or descriptor
+     * outside the string range, 64 base-case chunk too large, 128
+     * redistribution target outside its segment, 256 whole-GPU level tables
+     * full, 512 merge job rank out of range */
+    uint64_t error_bits;
 } ssort_stats_t;
 
 /* Create a context on HIP device `device` (the current device if < 0).
@@ -271,6 +280,7 @@ typedef struct {
     int status;          /* ssort_status of the job */
     double latency_ms;   /* submission to completion */
     double queue_ms;     /* submission to launch */
+    uint64_t device_error;   /* the launch's device error mask (ssort_stats_t.error_bits) */
 } ssort_result;
 
 /* Optional limits (0 = default): pinned staging bytes per slot and direction

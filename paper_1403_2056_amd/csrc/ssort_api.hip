@@ -468,6 +468,7 @@ ssort_status ssort_stats(ssort_ctx *ctx, ssort_stats_t *out, void *stream) {
     out->max_task = c.st[ST_MAX_TASK];
     out->max_chunk = c.st[ST_MAX_CHUNK];
     out->published_chunks = c.st[ST_PUBCHUNKS];
+    out->error_bits = c.error;
     return SSORT_OK;
 }
 

@@ -52,7 +52,21 @@ enum { PH_WAIT = 0, PH_SAMPLE = 1, PH_CLASSIFY = 2, PH_SCATTER = 3, PH_CHILDREN 
        PH_EXTEND = 6, PH_OTHER = 7, PH_BEXT = 8, PH_BKEY = 9, PH_BRANK = 10,
        PH_DRAIN = 11 };
 
-enum : unsigned long long { ERR_TIMEOUT = 1, ERR_BOUNDS = 2, ERR_ZERO = 4, ERR_QUEUE = 8, ERR_INTERNAL = 16 };
+// Device error bits (the mask reads back through the statistics): input
+// errors, the wait limit, and one bit per internal consistency check, each of
+// which ends the sort instead of letting an access leave its buffer.
+enum : unsigned long long {
+    ERR_TIMEOUT = 1,     // a work-queue wait exceeded its limit
+    ERR_BOUNDS = 2,      // a string lies outside the character buffer (validation)
+    ERR_ZERO = 4,        // a string holds the byte 0 (validation)
+    ERR_QUEUE = 8,       // a ring slot to fill still held an unconsumed task
+    ERR_DESC_CAP = 16,   // the group-descriptor array is full
+    ERR_TASK = 32,       // a task or group descriptor outside the string range
+    ERR_CHUNK = 64,      // a base-case chunk larger than the workgroup holds
+    ERR_SCATTER = 128,   // a redistribution target outside the segment's range
+    ERR_LEVEL = 256,     // a whole-GPU level's segment or tile table overflowed
+    ERR_MERGE = 512      // a merge job's rank beyond the sample count
+};
 
 // Task meta bits
 enum : uint32_t {

@@ -132,7 +132,7 @@ __device__ __forceinline__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, c
         const uint32_t mb = L.b[s];
         const uint32_t gp = run[mb] + (s - L.cs[mb]);
         if (gp < nlim) out[gp] = L.rec[s];
-        else atomicOr(err, ERR_INTERNAL);
+        else atomicOr(err, ERR_SCATTER);
     }
     __syncthreads();
     for (uint32_t b = tid; b < nb; b += NT) run[b] += L.tot[b];
@@ -840,7 +840,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
             const unsigned long long db = add_agent(&P.ctl->desc_top, (unsigned long long)nsmall);
             uint32_t npub = 0;
             if (db + nsmall > P.desc_cap) {
-                atomicOr(&P.ctl->error, ERR_INTERNAL);
+                atomicOr(&P.ctl->error, ERR_DESC_CAP);
                 L.nchunk = 0;
             } else if (cap) {
                 for (uint32_t c = 0; c < nchunk; ++c) {
@@ -958,13 +958,13 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
             }
             __syncthreads();
             ng = uni((ung > (uint32_t)NBPAD || L.qfail) ? 0u : ung);
-            if (ng == 0 && tid == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+            if (ng == 0 && tid == 0) atomicOr(&P.ctl->error, ERR_TASK);
             ung = 0;
         }
         if (ng) {
             const uint32_t M = uni(block_scan(L.psz, (int)ng, L.tmp, true, AddOp(), 0u));
             if (M > (uint32_t)C) {
-                if (tid == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+                if (tid == 0) atomicOr(&P.ctl->error, ERR_CHUNK);
             } else {
                 DescGroups g{L.bst, L.hist, L.gdep, L.psz};
                 base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, ng, M, g, [&](int i) { mark(L, i); }, L.st);
@@ -1025,7 +1025,7 @@ __global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
         if (threadIdx.x == 0) st_rlx(&s->seq, pos + P.ring_mask + 1);
         const unsigned long long t_task = wall_clock64();
         if (t.begin > P.S.n || t.size > P.S.n - t.begin) {
-            if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+            if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_TASK);
         } else {
             run_task<K, C>(P, t, L);
         }
@@ -1116,7 +1116,7 @@ __device__ void lvl_append(const Params &P, uint32_t l, const LvlSeg &g0) {
     const unsigned long long idx = add_agent(&P.ctl->lvl[l][0], 1ull);
     const unsigned long long t0 = add_agent(&P.ctl->lvl[l][1], (unsigned long long)g.ntile);
     if (idx >= P.lmaxseg || t0 + g.ntile > P.lmaxtiles) {
-        atomicOr(&P.ctl->error, ERR_INTERNAL);
+        atomicOr(&P.ctl->error, ERR_LEVEL);
         return;
     }
     g.tile0 = (uint32_t)t0;
@@ -1196,12 +1196,12 @@ __global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
     if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 1)) return;
     const uint32_t seg = P.tile2seg[l][blockIdx.x];
     if (seg >= lvl_count(P, l, 0)) {
-        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_LEVEL);
         return;
     }
     const LvlSeg g = P.lseg[l][seg];
     if (g.begin > P.S.n || g.size > P.S.n - g.begin) {
-        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_LEVEL);
         return;
     }
     load_split(sp, &P.lsplit[l][seg]);
@@ -1305,12 +1305,12 @@ __global__ __launch_bounds__(NT) void k_lvl_scatter(Params P, uint32_t l) {
     if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 1)) return;
     const uint32_t seg = P.tile2seg[l][blockIdx.x];
     if (seg >= lvl_count(P, l, 0)) {
-        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_LEVEL);
         return;
     }
     const LvlSeg g = P.lseg[l][seg];
     if (g.begin > P.S.n || g.size > P.S.n - g.begin) {
-        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_LEVEL);
         return;
     }
     load_split(L.sp, &P.lsplit[l][seg]);
@@ -1439,7 +1439,7 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
             L.pos = add_agent(&P.ctl->tail, nt);
         }
         L.db = nsmall ? add_agent(&P.ctl->desc_top, (unsigned long long)nsmall) : 0ull;
-        if (L.db + nsmall > P.desc_cap) atomicOr(&P.ctl->error, ERR_INTERNAL);
+        if (L.db + nsmall > P.desc_cap) atomicOr(&P.ctl->error, ERR_DESC_CAP);
     }
     __syncthreads();
     const unsigned long long pos = uni64(L.pos), db = uni64(L.db);

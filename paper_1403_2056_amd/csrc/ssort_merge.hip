@@ -15,6 +15,7 @@
 // without touching the strings.  A last pass computes the LCP across job
 // boundaries.
 #include "ssort_dev.h"
+#include "ssort_kernels.h"
 
 namespace ssm {
 
@@ -122,7 +123,7 @@ __global__ void k_msample(MergeParams M) {
         order += samples_below(c, M.g);
     }
     if (order >= M.nsamp) {
-        atomicOr(M.err, 16ull);
+        atomicOr(M.err, ssd::ERR_MERGE);
         return;
     }
     for (uint32_t r = 0; r < M.K; ++r) M.cuts[(size_t)order * M.K + r] = cut[r];

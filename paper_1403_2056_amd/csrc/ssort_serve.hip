@@ -36,6 +36,7 @@ struct JobRec {
     clk::time_point t_submit, t_start, t_done;
     int state = 0;          // 0 waiting, 1 running, 2 done, 3 cancelled
     ssort_status status = SSORT_OK;
+    uint64_t device_error = 0;   // the launch's device error mask
 };
 
 struct LaunchSlot {
@@ -258,6 +259,11 @@ struct ssort_server {
 
     void complete(LaunchSlot &s, const PackLayout &L) {
         ssort_status dev_rc = ssort_query_error(s.ctx, s.stream);
+        uint64_t bits = 0;
+        if (dev_rc != SSORT_OK) {
+            ssort_stats_t sst;
+            if (ssort_stats(s.ctx, &sst, s.stream) == SSORT_OK) bits = sst.error_bits;
+        }
         const uint32_t *perm = s.stage_out;
         const uint32_t *lcp = (const uint32_t *)((const uint8_t *)s.stage_out + (L.lcp - L.perm));
         pool->run(s.jobs.size(), [&](size_t k) {
@@ -270,6 +276,7 @@ struct ssort_server {
         for (uint32_t k = 0; k < s.jobs.size(); ++k) {
             JobRec &r = jobs[s.jobs[k]];
             if (r.status == SSORT_OK) r.status = dev_rc;
+            r.device_error = bits;
             r.state = 2;
             r.t_done = now;
             st.completed++;
@@ -401,6 +408,7 @@ ssort_status ssort_server_wait(ssort_server *S, uint64_t ticket, int timeout_ms,
         res->status = r.status;
         res->latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
         res->queue_ms = r.state == 2 ? std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count() : 0.0;
+        res->device_error = r.device_error;
     }
     const ssort_status rc = r.state == 3 ? SSORT_ENOTFOUND : r.status;
     S->jobs.erase(it);

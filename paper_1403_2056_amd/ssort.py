@@ -50,7 +50,7 @@ class Stats(ctypes.Structure):
                 ("phase_ticks", ctypes.c_uint64 * 16),
                 ("base_chunks", ctypes.c_uint64), ("base_rounds", ctypes.c_uint64),
                 ("max_task", ctypes.c_uint64), ("max_chunk", ctypes.c_uint64),
-                ("published_chunks", ctypes.c_uint64)]
+                ("published_chunks", ctypes.c_uint64), ("error_bits", ctypes.c_uint64)]
 
 
 PHASES = ["wait", "sample", "classify", "scatter", "children", "base", "extend", "other",
@@ -65,7 +65,7 @@ class Job(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int), ("latency_ms", ctypes.c_double),
-                ("queue_ms", ctypes.c_double)]
+                ("queue_ms", ctypes.c_double), ("device_error", ctypes.c_uint64)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -290,7 +290,7 @@ class Sorter:
         _check(lib().ssort_stats(self._h, ctypes.byref(st), _stream(stream)), "ssort_stats")
         return {"segments": st.segments, "strings": st.strings, "base_groups": st.base_groups,
                 "max_depth": st.max_depth, "base_chunks": st.base_chunks, "base_rounds": st.base_rounds,
-                "published_chunks": st.published_chunks,
+                "published_chunks": st.published_chunks, "error_bits": st.error_bits,
                 "max_task": {"ticks": st.max_task >> 24, "strings": st.max_task & 0xFFFFFF},
                 "max_chunk": {"ticks": st.max_chunk >> 24, "rounds": (st.max_chunk >> 12) & 0xFFF,
                               "strings": st.max_chunk & 0xFFF},
@@ -389,7 +389,8 @@ class Server:
         r = Result()
         rc = lib().ssort_server_wait(self._h, ticket, timeout_ms, ctypes.byref(r))
         chars, off, perm, lcp, n = self._jobs.pop(ticket)
-        _check(rc, "ssort_server_wait")
+        _check(rc, f"ssort_server_wait (device error mask {r.device_error:#x})" if r.device_error
+               else "ssort_server_wait")
         return perm[:n], (lcp[:n] if lcp is not None else None), {"latency_ms": r.latency_ms, "queue_ms": r.queue_ms}
 
     def cancel(self, ticket: int) -> bool:
