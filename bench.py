@@ -277,6 +277,7 @@ def main():
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--tb", type=int, default=128)
     ap.add_argument("--equal", action="store_true", help="S5-Equal classification")
+    ap.add_argument("--alphabet", action="store_true", help="alphabet compression (packed character codes)")
     ap.add_argument("--workload", default="prefixes", help="plain mode: prefixes, suffixes or plain")
     ap.add_argument("--mode", choices=["plain", "batched", "serve", "merge"], default="plain")
     ap.add_argument("--runs", type=int, default=8, help="merge mode: number of sorted runs K")
@@ -305,7 +306,7 @@ def main():
     print(f"[bench] generated n={ss.n} N={len(ss.chars)} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     d = ssort.strings_to_device(ss)
     sorter = ssort.Sorter(0, v=args.v, keys_per_thread=args.k, base_threshold=args.tb,
-                          flags=ssort.SSORT_EQUAL if args.equal else 0)
+                          flags=(ssort.SSORT_EQUAL if args.equal else 0) | (ssort.SSORT_ALPHABET if args.alphabet else 0))
     sorter.profile(True)
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     lcp = torch.empty(n, dtype=torch.int32, device="cuda")

@@ -82,7 +82,14 @@ typedef struct {
  *                  SSORT_EQUAL: classify with an equality test at every tree
  *                  node and an early exit ("S5-Equal", fourth equality-check
  *                  variant of the implementation details of S5) instead of a
- *                  full descent and one equality test ("S5-Unroll"). */
+ *                  full descent and one equality test ("S5-Unroll").
+ *                  SSORT_ALPHABET: alphabet compression (outlook of the
+ *                  paper): a first pass finds the sigma' byte values that
+ *                  occur in the character buffer; keys then hold
+ *                  q = min(64 / b, 32) characters of b = ceil(log2(sigma'+1))
+ *                  bits (order-preserving codes, 0 = end of string) instead
+ *                  of 8 bytes, e.g. 21 DNA characters.  The permutation and
+ *                  LCP array are identical to those without the flag. */
 typedef struct {
     uint32_t v;
     uint32_t keys_per_thread;
@@ -92,6 +99,7 @@ typedef struct {
 
 #define SSORT_VALIDATE 1u
 #define SSORT_EQUAL 2u
+#define SSORT_ALPHABET 4u
 
 typedef struct ssort_ctx ssort_ctx;
 

@@ -36,8 +36,15 @@ uint64_t next_pow2(uint64_t x) {
     return p;
 }
 
+uint32_t grid_for(uint64_t work) {
+    uint64_t g = (work + NT - 1) / NT;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (uint32_t)g;
+}
+
 struct Layout {
-    size_t ctl, r0, r1, bkt, ring, lseg[LMAX], t2s[LMAX], lsplit[LMAX], ltot[LMAX], hist, desc, total;
+    size_t ctl, r0, r1, bkt, ring, lseg[LMAX], t2s[LMAX], lsplit[LMAX], ltot[LMAX], hist, desc, alpha, total;
     uint64_t cap;
     uint32_t maxseg, maxtiles, tile;
 };
@@ -78,6 +85,7 @@ Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     }
     L.hist = take(4 * (size_t)NBPAD * L.maxtiles);
     L.desc = take(sizeof(GroupDesc) * (size_t)n);   // at most one descriptor per base-case group
+    L.alpha = take(sizeof(Alphabet));
     L.total = off;
     return L;
 }
@@ -87,22 +95,29 @@ bool valid_tuning(const ssort_tuning &t) {
     if (v < 1 || v > VMAX || ((v + 1) & v) != 0) return false;
     if (t.keys_per_thread != 4 && t.keys_per_thread != 8) return false;
     if (t.base_threshold < 16 || t.base_threshold > (uint32_t)CH) return false;
-    if (t.flags & ~(SSORT_VALIDATE | SSORT_EQUAL)) return false;
+    if (t.flags & ~(SSORT_VALIDATE | SSORT_EQUAL | SSORT_ALPHABET)) return false;
     return true;
 }
 
 int chunk_for(uint32_t tbase) { return tbase <= 256 ? 512 : 1024; }
 
-template <int K, int C>
+template <int K, int C, bool Z>
 hipError_t worker_occupancy(int *nb) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, (const void *)k_worker<K, C>, NT, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, (const void *)k_worker<K, C, Z>, NT, 0);
+}
+
+template <bool Z>
+hipError_t occupancy_z(const ssort_tuning &t, int *nb) {
+    const int C = chunk_for(t.base_threshold);
+    if (t.keys_per_thread == 4) return C == 512 ? worker_occupancy<4, 512, Z>(nb) : worker_occupancy<4, 1024, Z>(nb);
+    return C == 512 ? worker_occupancy<8, 512, Z>(nb) : worker_occupancy<8, 1024, Z>(nb);
 }
 
 hipError_t occupancy(const ssort_tuning &t, int *nb) {
-    const int C = chunk_for(t.base_threshold);
-    if (t.keys_per_thread == 4) return C == 512 ? worker_occupancy<4, 512>(nb) : worker_occupancy<4, 1024>(nb);
-    return C == 512 ? worker_occupancy<8, 512>(nb) : worker_occupancy<8, 1024>(nb);
+    return (t.flags & SSORT_ALPHABET) ? occupancy_z<true>(t, nb) : occupancy_z<false>(t, nb);
 }
+
+bool packed(const ssort_ctx *c) { return (c->tun.flags & SSORT_ALPHABET) != 0; }
 
 // Persistent workers: as many as fit on the GPU, but no more than the work
 // can use (about one per 512 strings, at least one per root task).
@@ -112,16 +127,35 @@ uint32_t worker_grid(const ssort_ctx *c, uint64_t n, uint64_t roots) {
     return (uint32_t)std::min<uint64_t>(want, (uint64_t)c->worker_blocks);
 }
 
-void launch_worker(const ssort_ctx *c, const Params &P, uint32_t grid, hipStream_t s) {
+template <bool Z>
+void launch_worker_z(const ssort_ctx *c, const Params &P, uint32_t grid, hipStream_t s) {
     const int C = chunk_for(c->tun.base_threshold);
     const dim3 g(grid), b(NT);
     if (c->tun.keys_per_thread == 4) {
-        if (C == 512) hipLaunchKernelGGL((k_worker<4, 512>), g, b, 0, s, P);
-        else hipLaunchKernelGGL((k_worker<4, 1024>), g, b, 0, s, P);
+        if (C == 512) hipLaunchKernelGGL((k_worker<4, 512, Z>), g, b, 0, s, P);
+        else hipLaunchKernelGGL((k_worker<4, 1024, Z>), g, b, 0, s, P);
     } else {
-        if (C == 512) hipLaunchKernelGGL((k_worker<8, 512>), g, b, 0, s, P);
-        else hipLaunchKernelGGL((k_worker<8, 1024>), g, b, 0, s, P);
+        if (C == 512) hipLaunchKernelGGL((k_worker<8, 512, Z>), g, b, 0, s, P);
+        else hipLaunchKernelGGL((k_worker<8, 1024, Z>), g, b, 0, s, P);
     }
+}
+
+void launch_worker(const ssort_ctx *c, const Params &P, uint32_t grid, hipStream_t s) {
+    if (packed(c)) launch_worker_z<true>(c, P, grid, s);
+    else launch_worker_z<false>(c, P, grid, s);
+}
+
+// Alphabet compression: the input's byte values and their codes, before
+// anything reads a key.
+void launch_alphabet(const ssort_ctx *c, const Params &P, hipStream_t s) {
+    if (!packed(c)) return;
+    hipLaunchKernelGGL(k_alpha_scan, dim3(grid_for(P.S.nchars / 8 + 1)), dim3(NT), 0, s, P);
+    hipLaunchKernelGGL(k_alpha_codes, dim3(1), dim3(NT), 0, s, P);
+}
+
+void launch_seam(const ssort_ctx *c, const Params &P, hipStream_t s) {
+    if (packed(c)) hipLaunchKernelGGL((k_seam<true>), dim3(grid_for(P.S.n)), dim3(NT), 0, s, P);
+    else hipLaunchKernelGGL((k_seam<false>), dim3(grid_for(P.S.n)), dim3(NT), 0, s, P);
 }
 
 // The whole-GPU levels (grids sized for each level's capacity; workgroups
@@ -129,10 +163,14 @@ void launch_worker(const ssort_ctx *c, const Params &P, uint32_t grid, hipStream
 // level 0 runs, without turning its buckets into tasks (the debug step).
 void launch_levels(const ssort_ctx *c, const Params &P, const Layout &L, bool schedule, hipStream_t s) {
     const int K = c->tun.keys_per_thread;
+    const bool z = packed(c) && P.alpha;
     for (uint32_t l = 0; l < (schedule ? (uint32_t)LMAX : 1u); ++l) {
-        hipLaunchKernelGGL(k_lvl_sample, dim3(L.maxseg), dim3(NT), 0, s, P, l);
-        if (K == 4) hipLaunchKernelGGL((k_lvl_classify<4>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
-        else hipLaunchKernelGGL((k_lvl_classify<8>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
+        if (z) hipLaunchKernelGGL((k_lvl_sample<true>), dim3(L.maxseg), dim3(NT), 0, s, P, l);
+        else hipLaunchKernelGGL((k_lvl_sample<false>), dim3(L.maxseg), dim3(NT), 0, s, P, l);
+        if (K == 4 && z) hipLaunchKernelGGL((k_lvl_classify<4, true>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
+        else if (K == 4) hipLaunchKernelGGL((k_lvl_classify<4, false>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
+        else if (z) hipLaunchKernelGGL((k_lvl_classify<8, true>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
+        else hipLaunchKernelGGL((k_lvl_classify<8, false>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), dim3(NT), 0, s, P, l);
         if (K == 4) hipLaunchKernelGGL((k_lvl_scatter<4>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         else hipLaunchKernelGGL((k_lvl_scatter<8>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
@@ -189,14 +227,8 @@ Params make_params(const ssort_ctx *c, const ssort_strings *in, uint32_t *perm, 
     P.equal = (c->tun.flags & SSORT_EQUAL) ? 1u : 0u;
     P.limit_ticks = (unsigned long long)c->wait_ms * c->wall_khz;
     P.limit_iters = (unsigned long long)c->wait_ms * 2000ull;   // polls take well over 0.5 us each
+    P.alpha = (c->tun.flags & SSORT_ALPHABET) ? (Alphabet *)(w + L.alpha) : nullptr;
     return P;
-}
-
-uint32_t grid_for(uint64_t work) {
-    uint64_t g = (work + NT - 1) / NT;
-    if (g < 1) g = 1;
-    if (g > 4096) g = 4096;
-    return (uint32_t)g;
 }
 
 }  // namespace
@@ -317,12 +349,13 @@ ssort_status ssort_sort(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_p
     if (ctx->prof) (void)hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, (unsigned long long)L.cap);
     if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
+    launch_alphabet(ctx, P, s);
     hipLaunchKernelGGL(k_seed, dim3(1), dim3(NT), 0, s, P, 1u, 0u, 0u);
     if (in->n > ROOT_MIN) launch_levels(ctx, P, L, true, s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[1], s);
     launch_worker(ctx, P, worker_grid(ctx, in->n, in->n > ROOT_MIN ? NBMAX : 1), s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[2], s);
-    if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(in->n)), dim3(NT), 0, s, P);
+    if (out_lcp) launch_seam(ctx, P, s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[3], s);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
@@ -343,12 +376,13 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
     if (ctx->prof) (void)hipEventRecord(ctx->ev[0], s);
     hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, (unsigned long long)L.cap);
     if (ctx->tun.flags & SSORT_VALIDATE) hipLaunchKernelGGL(k_validate, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
+    launch_alphabet(ctx, P, s);
     hipLaunchKernelGGL(k_seed, dim3(grid_for(m)), dim3(NT), 0, s, P, 2u, 0u, 0u);
     if (flat->n > ROOT_MIN) launch_levels(ctx, P, L, true, s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[1], s);
     launch_worker(ctx, P, worker_grid(ctx, flat->n, m), s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[2], s);
-    if (out_lcp) hipLaunchKernelGGL(k_seam, dim3(grid_for(flat->n)), dim3(NT), 0, s, P);
+    if (out_lcp) launch_seam(ctx, P, s);
     if (ctx->prof) (void)hipEventRecord(ctx->ev[3], s);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
@@ -484,6 +518,7 @@ ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t 
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
     Params P = make_params(ctx, in, perm, nullptr, ws, L, 1, nullptr);
+    P.alpha = nullptr;   // the dump reports 8-byte keys
     hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, (unsigned long long)L.cap);
     hipLaunchKernelGGL(k_seed, dim3(1), dim3(NT), 0, s, P, 1u, depth, 1u);
     launch_levels(ctx, P, L, false, s);

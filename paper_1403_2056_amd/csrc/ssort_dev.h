@@ -70,6 +70,78 @@ __device__ __forceinline__ uint64_t key_at(const uint8_t *chars, uint64_t nchars
     return k;
 }
 
+// Keys of a classification step, base-case round or seam: the next q
+// characters of a string from depth h in one uint64, first character in the
+// most significant bits, zero past the end, so that one unsigned compare
+// orders q characters and a zero last character means the string ends inside
+// the key.  ByteKey: q = 8 characters of 8 bits (the word of Algorithm 1).
+struct ByteKey {
+    __device__ __forceinline__ uint32_t q() const { return 8u; }
+    __device__ __forceinline__ uint64_t key(const Strs &S, uint64_t st, uint32_t ln, uint32_t h) const {
+        return key_at(S.chars, S.nchars, st, ln, h);
+    }
+    __device__ __forceinline__ bool ends(uint64_t k) const { return (k & 0xFF) == 0; }
+    // equal leading characters of two different keys (z = their xor != 0)
+    __device__ __forceinline__ uint32_t eqc(uint64_t z) const { return (uint32_t)(__clzll(z) >> 3); }
+};
+
+// Alphabet compression (the alphabet-compression idea of the paper's
+// outlook): when only sigma' < 256 byte values occur, character c gets the
+// order-preserving code 1 + (number of occurring values below c), the end of
+// the string code 0, so b = ceil(log2(sigma' + 1)) bits hold a character and
+// one key holds q = min(64 / b, 32) characters (21 for DNA instead of 8).
+// Keys compare exactly as the strings do; depths and LCPs stay in characters.
+struct Alphabet {
+    uint32_t b, q, sigma, pad;
+    uint32_t present[8];      // bitmap of the byte values that occur
+    uint8_t code[256];        // 0 for the value 0 and absent values, 1..sigma' in byte order
+};
+
+struct PackedKey {
+    const uint8_t *code;      // Alphabet::code in device memory (256 bytes: L1 hits)
+    uint32_t b, nq;
+    __device__ __forceinline__ uint32_t q() const { return nq; }
+    __device__ __forceinline__ uint64_t key(const Strs &S, uint64_t st, uint32_t ln, uint32_t h) const {
+        if (h >= ln) return 0;
+        const uint64_t p = st + h;
+        if (p >= S.nchars) return 0;
+        const uint32_t r = (uint32_t)min((uint64_t)min(ln - h, nq), S.nchars - p);
+        const uintptr_t a = (uintptr_t)(S.chars + p);
+        const uintptr_t a0 = a & ~(uintptr_t)7;
+        const uint32_t sh = (uint32_t)(a & 7);
+        const uint32_t nw = (sh + r + 7) >> 3;   // aligned words holding the r characters, 1..5
+        uint64_t w[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) w[i] = (uint32_t)i < nw ? *(const uint64_t *)(a0 + 8 * i) : 0ull;
+        // u0..u3: characters p + 8i .. p + 8i + 7 in little-endian byte order
+        const uint64_t u0 = sh ? (w[0] >> (8 * sh)) | (w[1] << (64 - 8 * sh)) : w[0];
+        const uint64_t u1 = sh ? (w[1] >> (8 * sh)) | (w[2] << (64 - 8 * sh)) : w[1];
+        const uint64_t u2 = sh ? (w[2] >> (8 * sh)) | (w[3] << (64 - 8 * sh)) : w[2];
+        const uint64_t u3 = sh ? (w[3] >> (8 * sh)) | (w[4] << (64 - 8 * sh)) : w[3];
+        uint64_t k = 0;
+        uint32_t at = 64;
+        // eight independent code loads per word, so that their latencies overlap
+#pragma unroll 1
+        for (uint32_t i = 0; 8 * i < r; ++i) {
+            const uint64_t x = i == 0 ? u0 : i == 1 ? u1 : i == 2 ? u2 : u3;
+            const uint32_t m = min(r - 8 * i, 8u);
+            uint32_t c8[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) c8[t] = (uint32_t)t < m ? code[(x >> (8 * t)) & 0xFF] : 0u;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if ((uint32_t)t < m) {
+                    at -= b;
+                    k |= (uint64_t)c8[t] << at;
+                }
+            }
+        }
+        return k;
+    }
+    __device__ __forceinline__ bool ends(uint64_t k) const { return ((k >> (64 - nq * b)) & ((1ull << b) - 1)) == 0; }
+    __device__ __forceinline__ uint32_t eqc(uint64_t z) const { return (uint32_t)__clzll(z) / b; }
+};
+
 // The 32 characters of a string from depth h as four keys (key_at at h,
 // h + 8, h + 16, h + 24), from the at most five aligned words that hold them.
 __device__ __forceinline__ void keys32_at(const uint8_t *chars, uint64_t nchars, uint64_t st, uint32_t ln, uint32_t h,
@@ -189,12 +261,12 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t *a, int len, uint32_t *t
 // Splitter set of one classification step (LDS or global copy).
 struct Split {
     uint64_t tree[VMAX + 1];   // level order, tree[1..v]
-    uint8_t hl[VMAX + 1];      // hl[l] = lcp(x[l-1], x[l]) in bytes, hl[0] = hl[v] = 0
-    uint8_t zr[VMAX + 1];      // zr[l] = x[l] ends its string (last byte zero)
+    uint8_t hl[VMAX + 1];      // hl[l] = lcp(x[l-1], x[l]) in characters, hl[0] = hl[v] = 0
+    uint8_t zr[VMAX + 1];      // zr[l] = x[l] ends its string (last character zero)
     uint32_t v, d, nb, nbits, ndistinct;
     uint32_t ulast;            // ranks >= ulast repeat x[ulast] (tree padded with the largest key)
     uint32_t equal;            // classify with an equality test at every node (S5-Equal)
-    uint32_t pad;
+    uint32_t q;                // characters per key (8, or more with alphabet compression)
 };
 
 // Level-order node of the splitter with in-order rank r in a perfect tree of
@@ -258,10 +330,10 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 // tree, the splitter LCPs (xor + count leading zeros) and the end-of-string
 // flags.  `samp`, `srt` need SAMPLE_MAX+1 entries (a power of two: the sort
 // pads to one), `fl` SAMPLE_MAX+1, tmp NW.
-template <typename Load>
+template <typename Load, typename KC>
 __device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
                                                  uint32_t equal, uint64_t *samp, uint64_t *srt, uint32_t *fl,
-                                                 uint32_t *tmp, Load load) {
+                                                 uint32_t *tmp, Load load, const KC &kc) {
     const int tid = tid_here();
     const uint32_t a = size < (uint32_t)(2 * (vmax + 1) - 1) ? size : (uint32_t)(2 * (vmax + 1) - 1);
     const bool all = size <= a;
@@ -325,6 +397,7 @@ __device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint3
         sp.ndistinct = U;
         sp.ulast = U <= vmax ? U - 1 : v;
         sp.equal = equal;
+        sp.q = kc.q();
     }
     __syncthreads();
     for (uint32_t j = 1 + tid; j <= v; j += NT) {
@@ -337,10 +410,10 @@ __device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint3
         uint32_t hl = 0;
         if (l > 0 && l < v) {
             const uint64_t z = samp[xsrc(l - 1)] ^ samp[xsrc(l)];
-            hl = z ? (uint32_t)(__clzll(z) >> 3) : 8u;
+            hl = z ? kc.eqc(z) : kc.q();
         }
         sp.hl[l] = (uint8_t)hl;
-        sp.zr[l] = (l < v && (samp[xsrc(l)] & 0xFF) == 0) ? 1 : 0;
+        sp.zr[l] = (l < v && kc.ends(samp[xsrc(l)])) ? 1 : 0;
     }
     __syncthreads();
 }

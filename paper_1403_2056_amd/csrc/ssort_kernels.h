@@ -114,7 +114,7 @@ struct Params {
     uint32_t equal;          // S5-Equal classification
     unsigned long long limit_ticks;
     unsigned long long limit_iters;
-
+    Alphabet *alpha;         // alphabet compression: codes of the input's byte values, else null
 };
 
 }  // namespace ssd

@@ -244,9 +244,9 @@ struct BaseLDS {
 
 // Group accessor: group g of the chunk has global start gstart(g), size
 // gsize(g), common depth gdepth(g) and chunk-local exclusive prefix gpre(g).
-template <int C, typename G, typename Mark>
+template <int C, typename G, typename Mark, typename KC>
 __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const Rec *src, uint32_t setbase,
-                           uint32_t ng, uint32_t M, const G &grp, Mark mk, unsigned long long *st) {
+                           uint32_t ng, uint32_t M, const G &grp, Mark mk, unsigned long long *st, const KC &kc) {
     const int tid = tid_here();
     auto find = [&](uint32_t q) -> uint32_t {
         uint32_t lo = 0, hi = ng;           // largest g with gpre(g) <= q
@@ -370,7 +370,7 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
                     const uint32_t e = B.ord[cur][q];
                     const uint32_t de = B.d[e];
                     on[u] = de != DONE;
-                    if (on[u]) kk[u] = key_at(P.S.chars, P.S.nchars, B.st[e], B.ln[e], de);
+                    if (on[u]) kk[u] = kc.key(P.S, B.st[e], B.ln[e], de);
                 }
             }
 #pragma unroll
@@ -408,12 +408,12 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
                 np[u] = c0 + less + eqb;
                 const uint32_t de = B.d[e];
                 if (eqb == 0) {
-                    if (less && P.lcp) P.lcp[gpos(np[u])] = de + (uint32_t)(__clzll(k ^ ml) >> 3);
-                } else if ((k & 0xFF) == 0) {
+                    if (less && P.lcp) P.lcp[gpos(np[u])] = de + kc.eqc(k ^ ml);
+                } else if (kc.ends(k)) {
                     if (P.lcp) P.lcp[gpos(np[u])] = B.ln[e];
                 }
-                const bool go = eqa >= 2 && (k & 0xFF) != 0;
-                B.d[e] = go ? de + 8 : DONE;
+                const bool go = eqa >= 2 && !kc.ends(k);
+                B.d[e] = go ? de + kc.q() : DONE;
                 if (go) B.any = 1;
                 // a run's first element marks a new class start
                 B.scr[np[u]] = eqb == 0 ? np[u] : 0u;
@@ -503,9 +503,10 @@ __device__ __forceinline__ void mark(LDS &L, int i) {
 
 // Common depth of bucket b's strings after a step at depth h (Algorithm 1's
 // output): h for the outer buckets b_0 and b_2v, h plus the splitter LCP for
-// the other range buckets, h + 8 for equality buckets.
+// the other range buckets, h + q (8 characters, or more with alphabet
+// compression) for equality buckets.
 __device__ __forceinline__ uint32_t child_depth(const Split &sp, uint32_t h, uint32_t b) {
-    if (b & 1) return h + 8;
+    if (b & 1) return h + sp.q;
     if (b == 0 || b == sp.nb - 1) return h;
     return h + sp.hl[b >> 1];
 }
@@ -592,23 +593,23 @@ __device__ __forceinline__ void finish_ident(const Params &P, const Rec *src, ui
 
 // One classification step of a segment by one workgroup.  Returns true when
 // `t` has been replaced by a child segment this workgroup continues with.
-template <int K, int C>
-__device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L) {
+template <int K, int C, typename KC>
+__device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L, const KC &kc) {
     const int tid = tid_here(), w = tid >> 6, lane = tid & 63;
     const uint32_t begin = t.begin, S = t.size, meta = t.meta;
     uint32_t h = t.depth;
     auto kload = [&](uint32_t e, uint32_t hh) -> uint64_t {
         const Rec r = load_rec(P, meta, begin + e);
-        return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
+        return kc.key(P.S, r.st, r.ln, hh);
     };
     // at most two samples: the second after a common-prefix extension (one
     // call site keeps the persistent kernel's code small)
 #pragma nounroll
     for (uint32_t pass = 0;; ++pass) {
     select_splitters(L.sp, S, h, hash32(begin * 0x85EBCA6Bu ^ h * 0xC2B2AE35u ^ S), P.vmax, P.equal, L.u.s.samp,
-                     L.u.s.srt, L.u.s.fl, L.tmp, kload);
+                     L.u.s.srt, L.u.s.fl, L.tmp, kload, kc);
     mark(L, PH_SAMPLE);
-    if (pass != 0 || uni(L.sp.ndistinct) != 1 || uni((uint32_t)(splitter(L.sp, 0) & 0xFF)) == 0) break;
+    if (pass != 0 || uni(L.sp.ndistinct) != 1 || uni((uint32_t)L.sp.zr[0]) != 0) break;
     {
         // Every sampled string has the same next 8 bytes: an equality chain.
         // Instead of one classification step per 8 equal bytes, find the
@@ -703,7 +704,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-            k[j] = (e < S) ? key_at(P.S.chars, P.S.nchars, r[j].st, r[j].ln, h) : 0;
+            k[j] = (e < S) ? kc.key(P.S, r[j].st, r[j].ln, h) : 0;
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -903,8 +904,8 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
     return false;
 }
 
-template <int K, int C>
-__device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> &L) {
+template <int K, int C, typename KC>
+__device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> &L, const KC &kc) {
     if (t.size == 0) return;
     if (t.meta & M_IDENT) {
         const Rec *src = (t.meta & M_PARITY) ? P.R1 : P.R0;
@@ -967,7 +968,7 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
                 if (tid == 0) atomicOr(&P.ctl->error, ERR_CHUNK);
             } else {
                 DescGroups g{L.bst, L.hist, L.gdep, L.psz};
-                base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, ng, M, g, [&](int i) { mark(L, i); }, L.st);
+                base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, ng, M, g, [&](int i) { mark(L, i); }, L.st, kc);
             }
             mark(L, PH_BASE);
             ng = 0;
@@ -983,7 +984,7 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
         }
         if (!seg) break;
         const bool to1 = out_is_r1(t.meta);
-        seg = seg_step<K, C>(P, t, L);
+        seg = seg_step<K, C>(P, t, L, kc);
         src = to1 ? P.R1 : P.R0;
         nchunk = uni(L.nchunk);
         db = uni64(L.dbase);
@@ -991,7 +992,18 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
     }
 }
 
-template <int K, int C>
+// The key codec of a launch: bytes, or the input's packed alphabet codes.
+template <bool Z> struct KeyOf;
+template <> struct KeyOf<false> {
+    static __device__ __forceinline__ ByteKey make(const Params &) { return ByteKey{}; }
+};
+template <> struct KeyOf<true> {
+    static __device__ __forceinline__ PackedKey make(const Params &P) {
+        return PackedKey{P.alpha->code, P.alpha->b, P.alpha->q};
+    }
+};
+
+template <int K, int C, bool Z>
 __global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
     __shared__ StepLDS<K, C> L;
     __shared__ unsigned long long claim;
@@ -1027,7 +1039,7 @@ __global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
         if (t.begin > P.S.n || t.size > P.S.n - t.begin) {
             if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_TASK);
         } else {
-            run_task<K, C>(P, t, L);
+            run_task<K, C>(P, t, L, KeyOf<Z>::make(P));
         }
         if (threadIdx.x == 0)
             L.st[ST_MAX_TASK] = max(L.st[ST_MAX_TASK], ((wall_clock64() - t_task) << 24) | min(t.size, 0xFFFFFFu));
@@ -1064,6 +1076,68 @@ __global__ void k_init(Params P, unsigned long long cap) {
         for (int l = 0; l < LMAX; ++l) c->lvl[l][0] = c->lvl[l][1] = 0;
         for (int k = 0; k < NST; ++k) c->st[k] = 0;
         for (int k = 0; k < NPH; ++k) c->ph[k] = 0;
+    }
+    if (P.alpha && i0 < 8) P.alpha->present[i0] = 0;
+}
+
+// Alphabet compression, first pass: the byte values that occur in the
+// character buffer (every aligned word that holds a byte of it; bytes outside
+// it are skipped; the value 0 ends strings and is never a character).  Each
+// thread keeps a 256-bit set in registers, then ORs it into the workgroup's
+// and the device's.
+__global__ __launch_bounds__(NT) void k_alpha_scan(Params P) {
+    __shared__ uint32_t bm[8];
+    if (threadIdx.x < 8) bm[threadIdx.x] = 0;
+    __syncthreads();
+    const uintptr_t a = (uintptr_t)P.S.chars, e = a + P.S.nchars;
+    const uintptr_t a0 = a & ~(uintptr_t)7;
+    const uint64_t nw = P.S.nchars ? (e + 7 - a0) >> 3 : 0;
+    uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)NT + threadIdx.x; i < nw; i += (uint64_t)gridDim.x * NT) {
+        const uintptr_t wa = a0 + 8 * i;
+        const uint64_t w = *(const uint64_t *)wa;
+        const bool whole = wa >= a && wa + 8 <= e;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint32_t c = (uint32_t)(w >> (8 * b)) & 0xFF;
+            const bool in = whole || (wa + b >= a && wa + b < e);
+            const uint64_t bit = in ? 1ull << (c & 63) : 0ull;
+            m0 |= (c >> 6) == 0 ? bit : 0ull;
+            m1 |= (c >> 6) == 1 ? bit : 0ull;
+            m2 |= (c >> 6) == 2 ? bit : 0ull;
+            m3 |= (c >> 6) == 3 ? bit : 0ull;
+        }
+    }
+    const uint64_t mm[4] = {m0, m1, m2, m3};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if ((uint32_t)mm[k]) atomicOr(&bm[2 * k], (uint32_t)mm[k]);
+        if ((uint32_t)(mm[k] >> 32)) atomicOr(&bm[2 * k + 1], (uint32_t)(mm[k] >> 32));
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && bm[threadIdx.x]) atomicOr(&P.alpha->present[threadIdx.x], bm[threadIdx.x]);
+}
+
+// Second pass (one workgroup): the order-preserving codes, bits per
+// character and characters per key.
+__global__ __launch_bounds__(NT) void k_alpha_codes(Params P) {
+    __shared__ uint32_t pres[8];
+    Alphabet *A = P.alpha;
+    if (threadIdx.x < 8) pres[threadIdx.x] = A->present[threadIdx.x] & (threadIdx.x == 0 ? ~1u : ~0u);
+    __syncthreads();
+    const uint32_t c = threadIdx.x;   // NT == 256 byte values
+    uint32_t below = 0;
+    for (uint32_t k = 0; k < (c >> 5); ++k) below += __popc(pres[k]);
+    below += __popc(pres[c >> 5] & ((1u << (c & 31)) - 1u));
+    const bool here = (pres[c >> 5] >> (c & 31)) & 1u;
+    A->code[c] = here ? (uint8_t)(below + 1) : (uint8_t)0;
+    if (c == 0) {
+        uint32_t sigma = 0;
+        for (int k = 0; k < 8; ++k) sigma += __popc(pres[k]);
+        const uint32_t b = sigma ? 32 - __clz(sigma) : 1u;   // values 0..sigma
+        A->sigma = sigma;
+        A->b = b;
+        A->q = min(64u / b, 32u);
     }
 }
 
@@ -1167,16 +1241,18 @@ struct LvlSampleLDS {
     uint32_t tmp[NW];
 };
 
+template <bool Z>
 __global__ __launch_bounds__(NT) void k_lvl_sample(Params P, uint32_t l) {
     __shared__ LvlSampleLDS L;
     if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 0)) return;
     const LvlSeg g = P.lseg[l][blockIdx.x];
+    const auto kc = KeyOf<Z>::make(P);
     auto kload = [&](uint32_t e, uint32_t hh) -> uint64_t {
         const Rec r = seg_rec(P, g.meta, g.begin + e);
-        return key_at(P.S.chars, P.S.nchars, r.st, r.ln, hh);
+        return kc.key(P.S, r.st, r.ln, hh);
     };
     select_splitters(L.sp, g.size, g.depth, hash32(g.begin * 0x85EBCA6Bu ^ g.depth * 0xC2B2AE35u ^ g.size), P.vmax,
-                     P.equal, L.samp, L.srt, L.fl, L.tmp, kload);
+                     P.equal, L.samp, L.srt, L.fl, L.tmp, kload, kc);
     const uint32_t *src = (const uint32_t *)&L.sp;
     uint32_t *dst = (uint32_t *)&P.lsplit[l][blockIdx.x];
     for (uint32_t i = threadIdx.x; i < sizeof(Split) / 4; i += NT) dst[i] = src[i];
@@ -1189,7 +1265,7 @@ __device__ void load_split(Split &sp, const Split *g) {
     __syncthreads();
 }
 
-template <int K>
+template <int K, bool Z>
 __global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
     __shared__ Split sp;
     __shared__ uint32_t hist[NBPAD];
@@ -1204,6 +1280,7 @@ __global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
         if (threadIdx.x == 0) atomicOr(&P.ctl->error, ERR_LEVEL);
         return;
     }
+    const auto kc = KeyOf<Z>::make(P);
     load_split(sp, &P.lsplit[l][seg]);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     for (int b = tid; b < NBPAD; b += NT) hist[b] = 0;
@@ -1225,7 +1302,7 @@ __global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-            k[j] = e < g.size ? key_at(P.S.chars, P.S.nchars, r[j].st, r[j].ln, g.depth) : 0;
+            k[j] = e < g.size ? kc.key(P.S, r[j].st, r[j].ln, g.depth) : 0;
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -1464,8 +1541,10 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
 // bucket created by a step at depth h; its predecessor lies in an earlier
 // bucket of that step, so their keys at depth h differ and the LCP is h plus
 // the equal leading bytes of the two keys.
+template <bool Z>
 __global__ void k_seam(Params P) {
     const uint32_t n = P.S.n;
+    const auto kc = KeyOf<Z>::make(P);
     for (uint32_t p = blockIdx.x * NT + threadIdx.x + 1; p < n; p += gridDim.x * NT) {
         const uint32_t v = P.lcp[p];
         if (!(v & SEAM)) continue;
@@ -1481,10 +1560,10 @@ __global__ void k_seam(Params P) {
         }
         const Rec a = make_rec(P.S, P.perm[p - 1] + base);
         const Rec b = make_rec(P.S, P.perm[p] + base);
-        const uint64_t ka = key_at(P.S.chars, P.S.nchars, a.st, a.ln, h);
-        const uint64_t kb = key_at(P.S.chars, P.S.nchars, b.st, b.ln, h);
+        const uint64_t ka = kc.key(P.S, a.st, a.ln, h);
+        const uint64_t kb = kc.key(P.S, b.st, b.ln, h);
         const uint64_t z = ka ^ kb;
-        P.lcp[p] = h + (z ? (uint32_t)(__clzll(z) >> 3) : 8u);
+        P.lcp[p] = h + (z ? kc.eqc(z) : kc.q());
     }
 }
 
@@ -1539,12 +1618,22 @@ __global__ void k_pack(const PackJob *jobs, const uint32_t *set_begin, uint32_t 
 }
 
 // explicit instantiations used by the host code
-template __global__ void k_worker<4, 512>(Params);
-template __global__ void k_worker<4, 1024>(Params);
-template __global__ void k_worker<8, 512>(Params);
-template __global__ void k_worker<8, 1024>(Params);
-template __global__ void k_lvl_classify<4>(Params, uint32_t);
-template __global__ void k_lvl_classify<8>(Params, uint32_t);
+template __global__ void k_worker<4, 512, false>(Params);
+template __global__ void k_worker<4, 1024, false>(Params);
+template __global__ void k_worker<8, 512, false>(Params);
+template __global__ void k_worker<8, 1024, false>(Params);
+template __global__ void k_worker<4, 512, true>(Params);
+template __global__ void k_worker<4, 1024, true>(Params);
+template __global__ void k_worker<8, 512, true>(Params);
+template __global__ void k_worker<8, 1024, true>(Params);
+template __global__ void k_lvl_sample<false>(Params, uint32_t);
+template __global__ void k_lvl_sample<true>(Params, uint32_t);
+template __global__ void k_lvl_classify<4, false>(Params, uint32_t);
+template __global__ void k_lvl_classify<8, false>(Params, uint32_t);
+template __global__ void k_lvl_classify<4, true>(Params, uint32_t);
+template __global__ void k_lvl_classify<8, true>(Params, uint32_t);
+template __global__ void k_seam<false>(Params);
+template __global__ void k_seam<true>(Params);
 template __global__ void k_lvl_scatter<4>(Params, uint32_t);
 template __global__ void k_lvl_scatter<8>(Params, uint32_t);
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libssort.so")
 SSORT_TO_END = 1
 SSORT_VALIDATE = 1
 SSORT_EQUAL = 2
+SSORT_ALPHABET = 4
 
 STATUS = {
     0: "SSORT_OK", 1: "SSORT_EINVAL", 2: "SSORT_ENOMEM", 3: "SSORT_EWORKSPACE", 4: "SSORT_EBOUNDS",

@@ -267,3 +267,53 @@ def test_batched_large_sets(sorter):
         rp, rh = oracle.sort(W.from_list(st))
         assert np.array_equal(p[a:b], rp), k
         assert np.array_equal(h[a:b], rh), k
+
+
+def _alphabet_inputs():
+    rng = np.random.default_rng(80)
+    dna = W.suffixes(1 << 18, seed=81)                      # 4 symbols: 21 characters per key
+    yield dna, "DNA suffixes 2^18"
+    yield W.prefixes(1 << 17, seed=82, n_prefix=64), "prefixes 2^17 (64 symbols: 9 per key)"
+    yield W.plain(100000, seed=83), "plain 100000 (26 symbols: 12 per key)"
+    yield W.from_list([b"a" * int(k) for k in rng.integers(0, 90, 5000)]), "one symbol (32 per key)"
+    yield W.from_list([bytes(rng.integers(97, 100, size=int(rng.integers(0, 70))).astype(np.uint8))
+                       for _ in range(40000)]), "three symbols (32 per key)"
+    yield W.from_list([bytes(rng.integers(1, 256, size=int(rng.integers(0, 30))).astype(np.uint8))
+                       for _ in range(20000)]), "255 symbols (8 per key)"
+    for strs in ([b"a"], [b"", b""], [b"x"] * 3, [b"", b"a", b""], [b"abc", b"ab", b"abd"]):
+        yield W.from_list(strs), f"tiny {strs}"
+    for seed in range(6):
+        r = np.random.default_rng(2000 + seed)
+        yield W.from_list(adversarial(r, int(r.integers(2, 6000)))), f"adversarial {seed}"
+
+
+@pytest.mark.parametrize("v,k,tb", [(255, 4, 128), (63, 8, 64), (7, 4, 512)])
+def test_alphabet_compression(v, k, tb):
+    """Keys of packed order-preserving character codes (ceil(log2(sigma'+1))
+    bits each): the same permutation and LCP array as the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_2056_amd import ssort
+    s = ssort.Sorter(0, v=v, keys_per_thread=k, base_threshold=tb, flags=ssort.SSORT_ALPHABET)
+    s.set_wait_limit(10000)
+    for ss, label in _alphabet_inputs():
+        assert_parity(s, ss, f"alphabet v={v} k={k} tb={tb} {label}")
+
+
+def test_alphabet_compression_batched(sorter):
+    """Batched sets (each below the whole-GPU level threshold) with packed keys."""
+    from paper_1403_2056_amd import ssort
+    s = ssort.Sorter(0, flags=ssort.SSORT_ALPHABET)
+    s.set_wait_limit(10000)
+    ss, sb = W.batched(m=48, seed=84, lo=0, hi=12)
+    d = ssort.strings_to_device(ss)
+    perm, lcp = s.sort_batched(d, torch.from_numpy(sb.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    assert s.query_error() == 0
+    p, h = ssort.to_numpy_u32(perm), ssort.to_numpy_u32(lcp)
+    strs = ss.strings()
+    for k in range(len(sb) - 1):
+        a, b = int(sb[k]), int(sb[k + 1])
+        rp, rh = oracle.sort(W.from_list(strs[a:b]))
+        assert np.array_equal(p[a:b], rp), k
+        assert np.array_equal(h[a:b], rh), k

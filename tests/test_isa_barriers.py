@@ -47,7 +47,7 @@ def test_worker_without_spills(asm):
     text = asm.read_text()
     blocks = re.findall(r"\.name:\s+(\S+)\n(?:.*\n){0,40}?\s+\.private_segment_fixed_size:\s+(\d+)", text)
     workers = {n: int(sz) for n, sz in blocks if "k_worker" in n}
-    assert len(workers) == 4, workers
+    assert len(workers) == 8, workers   # K in {4, 8} x chunk in {512, 1024} x byte or packed keys
     assert all(sz == 0 for sz in workers.values()), workers
 
 
@@ -62,6 +62,8 @@ def test_worker_code_fits_instruction_cache(asm, tmp_path):
         f = ln.split()
         if len(f) >= 8 and f[3] == "FUNC" and "k_worker" in f[7]:
             size[f[7]] = int(f[2])
-    assert len(size) == 4, size
-    default = [v for k, v in size.items() if "ILi4ELi512E" in k]
-    assert default and default[0] < 64 * 1024, size
+    assert len(size) == 8, size
+    # the default worker (K = 4, chunk 512) and its alphabet-compression twin
+    for z in ("Lb0E", "Lb1E"):
+        w = [v for k, v in size.items() if "ILi4ELi512E" + z in k]
+        assert w and w[0] < 64 * 1024, size
