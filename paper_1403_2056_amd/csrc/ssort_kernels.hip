@@ -1184,18 +1184,25 @@ __device__ __forceinline__ Rec seg_rec(const Params &P, uint32_t meta, uint32_t 
 }
 
 // Append a segment to level l (its tiles get consecutive numbers).
-__device__ void lvl_append(const Params &P, uint32_t l, const LvlSeg &g0) {
+// Returns the segment's tile count once its record is written (0 on
+// overflow); with fill = false the caller maps the tiles (*idx, *t0).
+__device__ uint32_t lvl_append(const Params &P, uint32_t l, const LvlSeg &g0, bool fill = true, uint32_t *oidx = nullptr,
+                               uint32_t *ot0 = nullptr) {
     LvlSeg g = g0;
     g.ntile = (g.size + P.tile - 1) / P.tile;
     const unsigned long long idx = add_agent(&P.ctl->lvl[l][0], 1ull);
     const unsigned long long t0 = add_agent(&P.ctl->lvl[l][1], (unsigned long long)g.ntile);
     if (idx >= P.lmaxseg || t0 + g.ntile > P.lmaxtiles) {
         atomicOr(&P.ctl->error, ERR_LEVEL);
-        return;
+        return 0;
     }
     g.tile0 = (uint32_t)t0;
     P.lseg[l][idx] = g;
-    for (uint32_t j = 0; j < g.ntile; ++j) P.tile2seg[l][t0 + j] = (uint32_t)idx;
+    if (fill)
+        for (uint32_t j = 0; j < g.ntile; ++j) P.tile2seg[l][t0 + j] = (uint32_t)idx;
+    if (oidx) *oidx = (uint32_t)idx;
+    if (ot0) *ot0 = (uint32_t)t0;
+    return g.ntile;
 }
 
 // Put a worker task at a queue position reserved before the workers start
@@ -1217,20 +1224,30 @@ __device__ __forceinline__ uint32_t lvl_count(const Params &P, uint32_t l, int w
 // Level 0: the whole input (mode 1) or every batched set (mode 2); a segment
 // of at most ROOT_MIN strings (unless force) goes straight to the workers.
 __global__ void k_seed(Params P, uint32_t mode, uint32_t depth, uint32_t force) {
-    if (P.ctl->error) return;
-    const uint32_t nset = mode == 1 ? 1u : P.m;
+    __shared__ uint32_t whole[3];   // mode 1: the input's level-0 segment, its first tile, its tile count
+    if (threadIdx.x == 0) whole[2] = 0;
+    __syncthreads();
+    const uint32_t nset = P.ctl->error ? 0u : (mode == 1 ? 1u : P.m);
     for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < nset; i += gridDim.x * NT) {
         const uint32_t b = mode == 1 ? 0u : P.set_begin[i], e = mode == 1 ? P.S.n : P.set_begin[i + 1];
         if (e <= b) continue;
         if (P.lcp) P.lcp[b] = 0;
         const uint32_t setbase = mode == 2 ? b : 0u;
         if (force || e - b > ROOT_MIN) {
-            lvl_append(P, 0, LvlSeg{b, e - b, depth, M_IDENT_SRC, 0, 0, setbase, 0});
+            // the whole input (one launch of one workgroup) maps its tiles with every thread below
+            if (mode == 1)
+                whole[2] = lvl_append(P, 0, LvlSeg{b, e - b, depth, M_IDENT_SRC, 0, 0, setbase, 0}, false, &whole[0],
+                                      &whole[1]);
+            else
+                lvl_append(P, 0, LvlSeg{b, e - b, depth, M_IDENT_SRC, 0, 0, setbase, 0});
         } else {
             add_agent(&P.ctl->pending, 1ull);
             seed_task(P, add_agent(&P.ctl->tail, 1ull), Task{b, e - b, depth, M_IDENT_SRC, setbase});
         }
     }
+    __syncthreads();
+    const uint32_t nt = whole[2];
+    for (uint32_t j = threadIdx.x; j < nt; j += NT) P.tile2seg[0][whole[1] + j] = whole[0];
 }
 
 struct LvlSampleLDS {
@@ -1545,25 +1562,53 @@ template <bool Z>
 __global__ void k_seam(Params P) {
     const uint32_t n = P.S.n;
     const auto kc = KeyOf<Z>::make(P);
-    for (uint32_t p = blockIdx.x * NT + threadIdx.x + 1; p < n; p += gridDim.x * NT) {
-        const uint32_t v = P.lcp[p];
-        if (!(v & SEAM)) continue;
-        const uint32_t h = v & ~SEAM;
-        uint32_t base = 0;
-        if (P.set_begin) {
-            uint32_t lo = 0, hi = P.m;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (P.set_begin[mid] <= p) lo = mid; else hi = mid;
-            }
-            base = P.set_begin[lo];
+    // SU positions per thread and trip, each stage's loads issued for all of
+    // them before the next stage needs the results (the lcp word, the two
+    // permutation entries, the two records, the two keys), so the dependent
+    // round trips overlap across positions instead of adding up
+    constexpr int SU = 4;
+    const uint32_t stride = gridDim.x * NT;
+    for (uint32_t p0 = blockIdx.x * NT + threadIdx.x + 1; p0 < n; p0 += SU * stride) {
+        uint32_t v[SU], ia[SU], ib[SU];
+        bool on[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const uint32_t p = p0 + u * stride;
+            v[u] = p < n ? P.lcp[p] : 0u;
+            on[u] = (v[u] & SEAM) != 0;
         }
-        const Rec a = make_rec(P.S, P.perm[p - 1] + base);
-        const Rec b = make_rec(P.S, P.perm[p] + base);
-        const uint64_t ka = kc.key(P.S, a.st, a.ln, h);
-        const uint64_t kb = kc.key(P.S, b.st, b.ln, h);
-        const uint64_t z = ka ^ kb;
-        P.lcp[p] = h + (z ? kc.eqc(z) : kc.q());
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            ia[u] = 0;
+            ib[u] = 0;
+            if (!on[u]) continue;
+            const uint32_t p = p0 + u * stride;
+            uint32_t base = 0;
+            if (P.set_begin) {
+                uint32_t lo = 0, hi = P.m;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (P.set_begin[mid] <= p) lo = mid; else hi = mid;
+                }
+                base = P.set_begin[lo];
+            }
+            ia[u] = P.perm[p - 1] + base;
+            ib[u] = P.perm[p] + base;
+        }
+        Rec ra[SU], rb[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            if (!on[u]) continue;
+            ra[u] = make_rec(P.S, ia[u]);
+            rb[u] = make_rec(P.S, ib[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            if (!on[u]) continue;
+            const uint32_t h = v[u] & ~SEAM;
+            const uint64_t z = kc.key(P.S, ra[u].st, ra[u].ln, h) ^ kc.key(P.S, rb[u].st, rb[u].ln, h);
+            P.lcp[p0 + u * stride] = h + (z ? kc.eqc(z) : kc.q());
+        }
     }
 }
 
