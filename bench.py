@@ -104,6 +104,14 @@ def bench_merge(args):
     print(json.dumps(out), flush=True)
 
 
+def device_error_exit(sorter, stream, what):
+    """Stop with the device error mask (which consistency check fired)."""
+    rc = sorter.query_error(stream)
+    if rc != 0:
+        bits = sorter.stats(stream)["error_bits"]
+        raise SystemExit(f"device error during {what}: status {rc}, error mask {bits:#x}")
+
+
 def bench_batched(args):
     """Batched form: 4096 independent sets (sizes 2^U(6,18), geometric lengths
     with mean 24, 95 printable bytes) sorted by one graph-captured launch,
@@ -112,7 +120,7 @@ def bench_batched(args):
     import torch
     from paper_1403_2056_amd import autotune, ssort, workloads
     t0 = time.time()
-    ss, sb = workloads.batched(m=args.sets, seed=5)
+    ss, sb = workloads.batched(m=args.sets, seed=5, hi=args.size_log2_max or 18)
     n = ss.n
     print(f"[bench] batched: {args.sets} sets, n={n}, N={len(ss.chars)} in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
@@ -135,6 +143,7 @@ def bench_batched(args):
             def run():
                 g.launch()
                 g.stream.synchronize()
+                device_error_exit(s, g.stream, f"autotune candidate {c}")
             run._keep = (s, g)
             return run
         tun, table = autotune.tune(factory, log=lambda m: print(m, file=sys.stderr, flush=True))
@@ -144,13 +153,13 @@ def bench_batched(args):
     for _ in range(args.warmup):
         g.launch()
     g.stream.synchronize()
-    assert sorter.query_error(g.stream) == 0
+    device_error_exit(sorter, g.stream, "batched graph warm-up")
     t1 = time.perf_counter()
     for _ in range(args.steps):
         g.launch()
     g.stream.synchronize()
     t_graph = (time.perf_counter() - t1) / args.steps
-    assert sorter.query_error(g.stream) == 0
+    device_error_exit(sorter, g.stream, "batched graph")
     # one set at a time, each sort synchronised before the next
     plain = ssort.Sorter(0, **tun)
     perm1 = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -173,7 +182,7 @@ def bench_batched(args):
     out = {"metric": "strings/sec batched (one graph launch) vs one-at-a-time", "value": round(n / t_graph, 1),
            "unit": "strings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(t_graph * 1000, 3), "higher_is_better": True, "dtype": "u8", "data": "synthetic",
-           "config": {"workload": f"batched: {args.sets} sets of 2^U(6,18) strings, geometric lengths mean 24, "
+           "config": {"workload": f"batched: {args.sets} sets of 2^U(6,{args.size_log2_max or 18}) strings, geometric lengths mean 24, "
                                   "95 printable bytes", "n": n, "N": int(len(ss.chars)), "tuning": tun},
            "one_at_a_time_ms": round(t_one * 1000, 3), "one_at_a_time_strings_per_s": round(n / t_one, 1),
            "batched_vs_one_at_a_time": round(t_one / t_graph, 2),
@@ -217,7 +226,7 @@ def bench_serve(args):
     jobs = []
     t0 = time.time()
     for _ in range(args.jobs):
-        nj = int(np.floor(2.0 ** rng.uniform(4, 20)))
+        nj = int(np.floor(2.0 ** rng.uniform(4, args.size_log2_max or 20)))
         jobs.append(workloads.mixed_job(rng, nj))
     ntot = sum(j.n for j in jobs)
     print(f"[bench] serve: {args.jobs} jobs, {ntot} strings, generated in {time.time() - t0:.1f}s",
@@ -257,7 +266,7 @@ def bench_serve(args):
     out = {"metric": "served jobs/s and p50/p99 latency, continuous batching vs one-job-at-a-time",
            "value": sat["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "higher_is_better": True,
            "dtype": "u8", "data": "synthetic",
-           "config": {"workload": f"{args.jobs} Poisson jobs, sizes 2^U(4,20), plain/long-prefix/suffix mix",
+           "config": {"workload": f"{args.jobs} Poisson jobs, sizes 2^U(4,{args.size_log2_max or 20}), plain/long-prefix/suffix mix",
                       "strings": ntot, "budget_gb": args.budget_gb},
            "served_saturated": sat, "served_at_0.7x": lat, "one_at_a_time": one, "one_at_a_time_at_0.7x": one_lat,
            "throughput_vs_one_at_a_time": round(sat["jobs_per_s"] / mu1, 2)}
@@ -282,6 +291,8 @@ def main():
     ap.add_argument("--mode", choices=["plain", "batched", "serve", "merge"], default="plain")
     ap.add_argument("--runs", type=int, default=8, help="merge mode: number of sorted runs K")
     ap.add_argument("--sets", type=int, default=4096)
+    ap.add_argument("--size-log2-max", type=int, default=0,
+                    help="batched/serve: largest set or job size exponent (default 18 / 20)")
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--jobs", type=int, default=600)
     ap.add_argument("--budget-gb", type=int, default=64)

@@ -1558,8 +1558,14 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
 // bucket created by a step at depth h; its predecessor lies in an earlier
 // bucket of that step, so their keys at depth h differ and the LCP is h plus
 // the equal leading bytes of the two keys.
+//
+// After a device error the workers stop early and leave permutation entries
+// unwritten (the outputs are undefined then), so the pass does not run: an
+// unwritten entry is not a string index.  An index outside a set is a device
+// error too, never an access.
 template <bool Z>
 __global__ void k_seam(Params P) {
+    if (P.ctl->error) return;
     const uint32_t n = P.S.n;
     const auto kc = KeyOf<Z>::make(P);
     // SU positions per thread and trip, each stage's loads issued for all of
@@ -1594,6 +1600,10 @@ __global__ void k_seam(Params P) {
             }
             ia[u] = P.perm[p - 1] + base;
             ib[u] = P.perm[p] + base;
+            if (ia[u] >= n || ib[u] >= n) {
+                atomicOr(&P.ctl->error, ERR_TASK);
+                on[u] = false;
+            }
         }
         Rec ra[SU], rb[SU];
 #pragma unroll

@@ -71,6 +71,13 @@ __global__ void k_mcache(MergeParams M) {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < M.n; p += gridDim.x * blockDim.x) {
         bool first = false;
         for (uint32_t k = 0; k < M.K; ++k) first |= (M.rb[k] == p);
+        // every later kernel reads strings through these indices: one outside
+        // the set ends the merge with a device error (they check it first)
+        if (M.pin[p] >= M.S.n) {
+            atomicOr(M.err, ssd::ERR_TASK);
+            M.cache[p] = 0;
+            continue;
+        }
         M.cache[p] = str_key(M, M.pin[p], first ? 0u : M.hin[p]);
     }
 }
@@ -84,7 +91,7 @@ __device__ __forceinline__ uint32_t samples_below(uint32_t c, uint32_t g) { retu
 // minimum), and its position in sample order.
 __global__ void k_msample(MergeParams M) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= M.nsamp) return;
+    if (t >= M.nsamp || *M.err) return;
     // which run and position: samples of run k are numbered from the
     // running total of earlier runs' samples
     uint32_t k = 0, base = 0;
@@ -189,7 +196,7 @@ __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t 
 __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     __shared__ MergeLDS L;
     const uint32_t j = blockIdx.x * MNT + threadIdx.x;
-    if (j >= M.nsamp) return;
+    if (j >= M.nsamp || *M.err) return;
     const int me = threadIdx.x;
     const uint32_t K = M.K;
     uint32_t KP = 1;
@@ -301,7 +308,7 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
 // LCP between the first output of each job and the string before it.
 __global__ void k_mseam(MergeParams M) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M.nsamp) return;
+    if (j >= M.nsamp || *M.err) return;
     uint32_t q = 0;
     for (uint32_t r = 0; r < M.K; ++r) q += M.cuts[(size_t)j * M.K + r];
     uint32_t qe = M.n;
