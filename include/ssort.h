@@ -138,7 +138,8 @@ typedef struct {
      * still occupied, 16 group-descriptor array full, 32 task or descriptor
      * outside the string range, 64 base-case chunk too large, 128
      * redistribution target outside its segment, 256 whole-GPU level tables
-     * full, 512 merge job rank out of range */
+     * full, 512 merge job rank or run index out of range, 1024 an output
+     * permutation entry outside its set at a bucket seam */
     uint64_t error_bits;
 } ssort_stats_t;
 

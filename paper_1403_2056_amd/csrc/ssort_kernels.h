@@ -65,7 +65,8 @@ enum : unsigned long long {
     ERR_CHUNK = 64,      // a base-case chunk larger than the workgroup holds
     ERR_SCATTER = 128,   // a redistribution target outside the segment's range
     ERR_LEVEL = 256,     // a whole-GPU level's segment or tile table overflowed
-    ERR_MERGE = 512      // a merge job's rank beyond the sample count
+    ERR_MERGE = 512,     // a merge job's rank beyond the sample count, or a run index outside the set
+    ERR_SEAM = 1024      // an output permutation entry outside its set at a bucket seam
 };
 
 // Task meta bits

@@ -1601,7 +1601,7 @@ __global__ void k_seam(Params P) {
             ia[u] = P.perm[p - 1] + base;
             ib[u] = P.perm[p] + base;
             if (ia[u] >= n || ib[u] >= n) {
-                atomicOr(&P.ctl->error, ERR_TASK);
+                atomicOr(&P.ctl->error, ERR_SEAM);
                 on[u] = false;
             }
         }

@@ -74,7 +74,7 @@ __global__ void k_mcache(MergeParams M) {
         // every later kernel reads strings through these indices: one outside
         // the set ends the merge with a device error (they check it first)
         if (M.pin[p] >= M.S.n) {
-            atomicOr(M.err, ssd::ERR_TASK);
+            atomicOr(M.err, ssd::ERR_MERGE);
             M.cache[p] = 0;
             continue;
         }

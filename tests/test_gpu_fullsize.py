@@ -28,7 +28,7 @@ def run(sorter, ss):
     d = ssort.strings_to_device(ss)
     perm, lcp = sorter.sort(d)
     torch.cuda.synchronize()
-    assert sorter.query_error() == 0
+    assert sorter.query_error() == 0, sorter.stats()
     return ssort.to_numpy_u32(perm).copy(), ssort.to_numpy_u32(lcp).copy()
 
 

@@ -51,7 +51,7 @@ def merge_parity(sorter, ss, K, seed, label, contiguous=False):
     th = torch.from_numpy(hin.view(np.int32)).cuda()
     p, h = sorter.merge(d, rb, tp, th)
     torch.cuda.synchronize()
-    assert sorter.query_error() == 0
+    assert sorter.query_error() == 0, sorter.stats()
     rp, rh = oracle.sort(ss)
     p, h = ssort.to_numpy_u32(p), ssort.to_numpy_u32(h)
     if not np.array_equal(p, rp):

@@ -28,7 +28,7 @@ def gpu_sort(sorter, ss, with_lcp=True):
     perm, lcp = sorter.sort(d, with_lcp=with_lcp)
     torch.cuda.synchronize()
     err = sorter.query_error()
-    assert err == 0, f"device error {err}"
+    assert err == 0, f"device error {err}, error mask {sorter.stats()['error_bits']:#x}, stats {sorter.stats()}"
     p = ssort.to_numpy_u32(perm).copy()
     h = ssort.to_numpy_u32(lcp).copy() if with_lcp else None
     return p, h
@@ -207,7 +207,7 @@ def test_batched_small(sorter):
     sbt = torch.from_numpy(sb.view(np.int32)).cuda()
     perm, lcp = sorter.sort_batched(d, sbt)
     torch.cuda.synchronize()
-    assert sorter.query_error() == 0
+    assert sorter.query_error() == 0, sorter.stats()
     p, h = ssort.to_numpy_u32(perm), ssort.to_numpy_u32(lcp)
     strs = ss.strings()
     for s in range(len(sb) - 1):
@@ -260,7 +260,7 @@ def test_batched_large_sets(sorter):
     d = ssort.strings_to_device(ss)
     perm, lcp = sorter.sort_batched(d, torch.from_numpy(sb.view(np.int32)).cuda())
     torch.cuda.synchronize()
-    assert sorter.query_error() == 0
+    assert sorter.query_error() == 0, sorter.stats()
     p, h = ssort.to_numpy_u32(perm), ssort.to_numpy_u32(lcp)
     for k, st in enumerate(sets):
         a, b = int(sb[k]), int(sb[k + 1])
@@ -309,7 +309,7 @@ def test_alphabet_compression_batched(sorter):
     d = ssort.strings_to_device(ss)
     perm, lcp = s.sort_batched(d, torch.from_numpy(sb.view(np.int32)).cuda())
     torch.cuda.synchronize()
-    assert s.query_error() == 0
+    assert s.query_error() == 0, s.stats()
     p, h = ssort.to_numpy_u32(perm), ssort.to_numpy_u32(lcp)
     strs = ss.strings()
     for k in range(len(sb) - 1):

@@ -39,7 +39,7 @@ def test_graph_plain_replays(ss_mod):
         torch.cuda.synchronize()
         g.launch()
         g.stream.synchronize()
-        assert s.query_error(g.stream) == 0
+        assert s.query_error(g.stream) == 0, s.stats(g.stream)
         assert np.array_equal(u32(g.perm)[:ss.n], rp), rep
         assert np.array_equal(u32(g.lcp)[:ss.n], rh), rep
         # eager work between replays
@@ -69,7 +69,7 @@ def test_graph_batched_replays(ss_mod):
         torch.cuda.synchronize()
         g.launch()
         g.stream.synchronize()
-        assert s.query_error(g.stream) == 0
+        assert s.query_error(g.stream) == 0, s.stats(g.stream)
         p, h = u32(g.perm), u32(g.lcp)
         for k, (rp, rh) in enumerate(refs):
             a, b = int(sb[k]), int(sb[k + 1])
