@@ -26,9 +26,44 @@ struct Task {
     uint32_t begin, size, depth, meta, setbase;
 };
 
-__device__ __forceinline__ Rec load_rec(const Params &P, uint32_t meta, uint32_t pos) {
+// Data another workgroup wrote during this launch (a task's records, a
+// group descriptor, a queue slot) is read with device-coherent loads: on this
+// chip a die's L2 can still hold a line of it from before the writer's
+// release (a neighbouring range read earlier, or the previous sort in the same
+// memory), and the acquire does not drop such lines.  A workgroup's own
+// writes (the child it goes on with, its own chunks) use ordinary loads.
+__device__ __forceinline__ uint32_t ld_coh32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_coh64(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh32(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh64(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// A group descriptor handed to other workgroups: device-coherent stores.
+__device__ __forceinline__ void st_desc(GroupDesc *d, uint32_t start, uint32_t size, uint32_t depth) {
+    uint64_t *q = reinterpret_cast<uint64_t *>(d);
+    st_coh64(q, (uint64_t)start | ((uint64_t)size << 32));
+    st_coh64(q + 1, (uint64_t)depth);
+}
+__device__ __forceinline__ Rec ld_rec(const Rec *p, bool coh) {
+    if (!coh) return *p;
+    const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
+    const uint64_t a = ld_coh64(q), b = ld_coh64(q + 1);
+    Rec r;
+    r.st = a;
+    r.ln = (uint32_t)b;
+    r.id = (uint32_t)(b >> 32);
+    return r;
+}
+
+__device__ __forceinline__ Rec load_rec(const Params &P, uint32_t meta, uint32_t pos, bool coh) {
     if (meta & M_IDENT_SRC) return make_rec(P.S, pos);
-    return (meta & M_PARITY) ? P.R1[pos] : P.R0[pos];
+    return ld_rec(((meta & M_PARITY) ? P.R1 : P.R0) + pos, coh);
 }
 
 // A step writes its redistribution into the other record buffer.
@@ -54,10 +89,19 @@ __device__ __forceinline__ unsigned long long add_agent(unsigned long long *p, u
 // L2 and then a single wave releases (instead of every wave).  Whatever is
 // stored after this (queue slot sequence numbers) can be relaxed: a reader
 // that sees it and then acquires sees the data.
+//
+// The fence alone compiles to the L2 write-back without a wait for it: the
+// compiler leaves that wait to this wave's next store, but the publishing
+// stores that follow the barrier come from every wave.  So the releasing wave
+// waits for the write-back itself before the barrier; without that wait a
+// sequence number could become visible before the data it publishes.
 __device__ __forceinline__ void release_wg() {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
+    }
     __syncthreads();
 }
 
@@ -246,7 +290,8 @@ struct BaseLDS {
 // gsize(g), common depth gdepth(g) and chunk-local exclusive prefix gpre(g).
 template <int C, typename G, typename Mark, typename KC>
 __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint32_t *tmp, const Rec *src, uint32_t setbase,
-                           uint32_t ng, uint32_t M, const G &grp, Mark mk, unsigned long long *st, const KC &kc) {
+                           uint32_t ng, uint32_t M, const G &grp, Mark mk, unsigned long long *st, const KC &kc,
+                           bool coh) {
     const int tid = tid_here();
     auto find = [&](uint32_t q) -> uint32_t {
         uint32_t lo = 0, hi = ng;           // largest g with gpre(g) <= q
@@ -270,7 +315,7 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
             const uint32_t q = tid + u * NT;
             if (q < M) {
                 gg[u] = find(q);
-                rr[u] = src[grp.gstart(gg[u]) + (q - grp.gpre(gg[u]))];
+                rr[u] = ld_rec(&src[grp.gstart(gg[u]) + (q - grp.gpre(gg[u]))], coh);
             }
         }
 #pragma unroll
@@ -571,11 +616,11 @@ __device__ __forceinline__ void stage(const Params &P, unsigned long long pos, c
         *fail = 1;
         return;
     }
-    s->begin = t.begin;
-    s->size = t.size;
-    s->depth = t.depth;
-    s->meta = t.meta;
-    s->setbase = t.setbase;
+    st_coh32(&s->begin, t.begin);
+    st_coh32(&s->size, t.size);
+    st_coh32(&s->depth, t.depth);
+    st_coh32(&s->meta, t.meta);
+    st_coh32(&s->setbase, t.setbase);
 }
 __device__ __forceinline__ void commit(const Params &P, unsigned long long pos) {
     st_rlx(&P.ring[pos & P.ring_mask].seq, pos + 1);
@@ -594,12 +639,12 @@ __device__ __forceinline__ void finish_ident(const Params &P, const Rec *src, ui
 // One classification step of a segment by one workgroup.  Returns true when
 // `t` has been replaced by a child segment this workgroup continues with.
 template <int K, int C, typename KC>
-__device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L, const KC &kc) {
+__device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C> &L, const KC &kc, bool coh) {
     const int tid = tid_here(), w = tid >> 6, lane = tid & 63;
     const uint32_t begin = t.begin, S = t.size, meta = t.meta;
     uint32_t h = t.depth;
     auto kload = [&](uint32_t e, uint32_t hh) -> uint64_t {
-        const Rec r = load_rec(P, meta, begin + e);
+        const Rec r = load_rec(P, meta, begin + e, coh);
         return kc.key(P.S, r.st, r.ln, hh);
     };
     // at most two samples: the second after a common-prefix extension (one
@@ -620,7 +665,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
             L.nlist = 0;
         }
         __syncthreads();
-        const Rec f = load_rec(P, meta, begin);
+        const Rec f = load_rec(P, meta, begin, coh);
         uint64_t fk[4];
         keys32_at(P.S.chars, P.S.nchars, f.st, f.ln, h, fk);
         uint32_t *list = reinterpret_cast<uint32_t *>(L.u.s.samp);   // 4 * NT entries
@@ -632,7 +677,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
             Rec r[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (e0 + u * NT < S) r[u] = load_rec(P, meta, begin + e0 + u * NT);
+                if (e0 + u * NT < S) r[u] = load_rec(P, meta, begin + e0 + u * NT, coh);
             uint64_t k[4][4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -666,13 +711,13 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
                 for (uint32_t i0 = 0; i0 < n; i0 += NT / gw) {
                     const uint32_t i = i0 + tid / gw;
                     const bool on = i < n;
-                    const Rec q = load_rec(P, meta, begin + (on ? list[i] : 0u));
+                    const Rec q = load_rec(P, meta, begin + (on ? list[i] : 0u), coh);
                     const uint32_t l = group_lcp(P, gw, on, f.st, f.ln, q.st, q.ln, h + 32, &L.ext_min);
                     if (on && (tid & (gw - 1)) == 0) atomicMin(&L.ext_min, l);
                 }
             } else {
                 for (uint32_t i = tid; i < n; i += NT) {
-                    const Rec q = load_rec(P, meta, begin + list[i]);
+                    const Rec q = load_rec(P, meta, begin + list[i], coh);
                     atomicMin(&L.ext_min, lcp_from(P, f.st, f.ln, q.st, q.ln, h + 32, &L.ext_min));
                 }
             }
@@ -698,7 +743,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
-            if (e < S) r[j] = load_rec(P, meta, begin + e);
+            if (e < S) r[j] = load_rec(P, meta, begin + e, coh);
         }
         uint64_t k[K];
 #pragma unroll
@@ -732,7 +777,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
         for (int j = 0; j < K; ++j) {
             const uint32_t e = c0 + (uint32_t)(w * 64 * K + j * 64 + lane);
             if (e < S) {
-                r[j] = load_rec(P, meta, begin + e);
+                r[j] = load_rec(P, meta, begin + e, coh);
                 m[j] = P.bkt[begin + e];
             } else {
                 m[j] = nb;
@@ -867,7 +912,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
             const unsigned long long db = uni64(L.dbase);
             for (uint32_t k = tid; k < nsmall; k += NT) {
                 const uint32_t b = L.lsmall[k];
-                P.desc[db + k] = GroupDesc{begin + L.bst[b], L.hist[b], child_depth(L.sp, h, b), 0u};
+                st_desc(&P.desc[db + k], begin + L.bst[b], L.hist[b], child_depth(L.sp, h, b));
             }
             if (uni(L.npub)) {
                 for (uint32_t c = tid; c < nchunk; c += NT) {
@@ -920,6 +965,7 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
     uint32_t ng = 0;               // groups ready in the bucket arrays
     uint32_t nchunk = 0, c = 0;    // chunks of the last step, the next to look at
     unsigned long long db = 0;
+    bool coh = true;               // the data to read next was written by another workgroup
     const Rec *src = (t.meta & M_PARITY) ? P.R1 : P.R0;
     if (t.meta & M_CHUNK) {
         ud0 = t.begin;
@@ -930,6 +976,7 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
             for (uint32_t i = tid; i < t.size; i += NT) P.R0[t.begin + i] = make_rec(P.S, t.begin + i);
             __threadfence();
             src = P.R0;
+            coh = false;
         }
         if (tid == 0) {
             L.bst[0] = t.begin;
@@ -950,7 +997,14 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
             if (tid == 0) L.qfail = 0;
             __syncthreads();
             for (uint32_t g = tid; g < min(ung, (uint32_t)NBPAD); g += NT) {
-                const GroupDesc d = P.desc[ud0 + g];
+                GroupDesc d;
+                if (coh) {
+                    const uint64_t *q = reinterpret_cast<const uint64_t *>(&P.desc[ud0 + g]);
+                    const uint64_t a = ld_coh64(q), b = ld_coh64(q + 1);
+                    d = GroupDesc{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+                } else {
+                    d = P.desc[ud0 + g];
+                }
                 if (d.start > P.S.n || d.size > P.S.n - d.start || d.size == 0 || d.size > P.tbase) L.qfail = 1;
                 L.bst[g] = d.start;
                 L.hist[g] = d.size;
@@ -968,7 +1022,7 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
                 if (tid == 0) atomicOr(&P.ctl->error, ERR_CHUNK);
             } else {
                 DescGroups g{L.bst, L.hist, L.gdep, L.psz};
-                base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, ng, M, g, [&](int i) { mark(L, i); }, L.st, kc);
+                base_chunk<C>(P, L.u.base, L.tmp, src, t.setbase, ng, M, g, [&](int i) { mark(L, i); }, L.st, kc, coh);
             }
             mark(L, PH_BASE);
             ng = 0;
@@ -984,7 +1038,8 @@ __device__ __forceinline__ void run_task(const Params &P, Task t, StepLDS<K, C> 
         }
         if (!seg) break;
         const bool to1 = out_is_r1(t.meta);
-        seg = seg_step<K, C>(P, t, L, kc);
+        seg = seg_step<K, C>(P, t, L, kc, coh);
+        coh = false;   // the next child and the local chunks are this workgroup's own output
         src = to1 ? P.R1 : P.R0;
         nchunk = uni(L.nchunk);
         db = uni64(L.dbase);
@@ -1032,7 +1087,8 @@ __global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
         const int o = (int)uni((uint32_t)outcome);
         mark(L, o > 0 ? PH_WAIT : PH_DRAIN);
         if (o <= 0) break;
-        const Task t{uni(s->begin), uni(s->size), uni(s->depth), uni(s->meta), uni(s->setbase)};
+        const Task t{uni(ld_coh32(&s->begin)), uni(ld_coh32(&s->size)), uni(ld_coh32(&s->depth)),
+                     uni(ld_coh32(&s->meta)), uni(ld_coh32(&s->setbase))};
         __syncthreads();   // every wave has read the slot: hand it back to the ring
         if (threadIdx.x == 0) st_rlx(&s->seq, pos + P.ring_mask + 1);
         const unsigned long long t_task = wall_clock64();

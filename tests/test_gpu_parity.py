@@ -232,17 +232,10 @@ def _level_one_strings(seed):
     return strs
 
 
-SKIP_LEVEL_ONE = ("these inputs (80000 strings behind one key, through the second whole-GPU level with "
-                  "the 2^16 threshold) were running when a GPU run faulted; the cause is not found, so the "
-                  "case stays off the GPU (device bounds checks now turn a bad descriptor or tile into an error)")
-
-
-@pytest.mark.skip(reason=SKIP_LEVEL_ONE)
 def test_second_level(sorter):
     assert_parity(sorter, W.from_list(_level_one_strings(50)), "second whole-GPU level")
 
 
-@pytest.mark.skip(reason=SKIP_LEVEL_ONE)
 def test_batched_large_sets(sorter):
     """Sets above the whole-GPU threshold go through the levels, the others
     straight to the workers; every set equals its own oracle sort."""

@@ -120,12 +120,6 @@ def test_server_results_alone_and_in_mix(ss_mod):
     _check_mix(jobs, alone, mixed)
 
 
-SKIP_LARGE_BATCHED = ("a batched sort of 2^20 plain strings (one set, through the server) ended with a device "
-                      "error on the GPU; the cause is not found (the same input passes on the CPU emulation, "
-                      "sequential and with 16 concurrent workgroups), so the case stays off the GPU")
-
-
-@pytest.mark.skip(reason=SKIP_LARGE_BATCHED)
 def test_server_mix_behind_large_job(ss_mod):
     ssort = ss_mod
     jobs = _jobs(33, 40)
