@@ -310,3 +310,46 @@ def test_alphabet_compression_batched(sorter):
         rp, rh = oracle.sort(W.from_list(strs[a:b]))
         assert np.array_equal(p[a:b], rp), k
         assert np.array_equal(h[a:b], rh), k
+
+
+def test_batched_many_large_sets():
+    """1024 sets of up to 2^16 strings in one launch, with the tuning (v = 63,
+    base threshold 256) that publishes the most base-case chunks per step:
+    every set is a permutation of itself with no device error, three times
+    over, and sampled sets equal their oracle sort (a regression test for
+    work-queue hand-over: a publishing store overtaking the L2 write-back of
+    the data it publishes)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1403_2056_amd import ssort
+    ss, sb = W.batched(m=1024, seed=90, lo=6, hi=16)
+    print(f"[parity] many large sets n={ss.n}", flush=True)
+    s = ssort.Sorter(0, v=63, keys_per_thread=4, base_threshold=256)
+    s.set_wait_limit(10000)
+    d = ssort.strings_to_device(ss)
+    sbt = torch.from_numpy(sb.view(np.int32).copy()).cuda()
+    perm = torch.empty(ss.n, dtype=torch.int32, device="cuda")
+    lcp = torch.empty(ss.n, dtype=torch.int32, device="cuda")
+    sizes = np.diff(sb.astype(np.int64))
+    starts = sb[:-1].astype(np.int64)
+    rng = np.random.default_rng(91)
+    sample = rng.choice(len(sizes), size=12, replace=False)
+    for rep in range(3):
+        perm.fill_(-1)
+        s.sort_batched(d, sbt, out_perm=perm, out_lcp=lcp)
+        torch.cuda.synchronize()
+        assert s.query_error() == 0, s.stats()
+        p = ssort.to_numpy_u32(perm)
+        # each set's entries are a permutation of 0..size-1
+        ok = (p < np.repeat(sizes, sizes).astype(np.uint32))
+        assert ok.all(), (rep, int(np.argmin(ok)))
+        key = np.repeat(starts, sizes) + p.astype(np.int64)
+        assert np.array_equal(np.sort(key), np.arange(ss.n)), rep
+    h = ssort.to_numpy_u32(lcp)
+    o = ss.offsets
+    for k in sample:
+        a, n_k = int(starts[k]), int(sizes[k])
+        sub = W.from_list([ss.chars[int(o[j]):int(o[j + 1])].tobytes() for j in range(a, a + n_k)])
+        rp, rh = oracle.sort(sub)
+        assert np.array_equal(p[a:a + n_k], rp), k
+        assert np.array_equal(h[a:a + n_k], rh), k

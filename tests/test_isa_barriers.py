@@ -67,3 +67,40 @@ def test_worker_code_fits_instruction_cache(asm, tmp_path):
     for z in ("Lb0E", "Lb1E"):
         w = [v for k, v in size.items() if "ILi4ELi512E" + z in k]
         assert w and w[0] < 64 * 1024, size
+
+
+def _waited_before_barrier(body):
+    """Every L2 write-back (the agent-scope release) is followed by a wait for
+    the vector memory counter before the next barrier of the same straight
+    path: the stores that publish after the barrier come from every wave, so
+    the write-back must have finished by then.  Returns the offending lines."""
+    bad = []
+    for i, ln in enumerate(body):
+        if "buffer_wbl2" not in ln:
+            continue
+        waited = False
+        for nx in body[i + 1:]:
+            t = nx.strip()
+            if t.startswith("s_waitcnt") and ("vmcnt(0)" in t or t == "s_waitcnt 0"):
+                waited = True
+            if t.startswith("s_barrier") or t.startswith("s_endpgm"):
+                break
+        if not waited:
+            bad.append(i)
+    return bad
+
+
+def test_release_waits_for_writeback_before_barrier(asm):
+    lines = asm.read_text().splitlines()
+    kernels = [(k, body) for k, body in isa_barriers.kernels(lines) if "k_worker" in k]
+    assert len(kernels) == 8
+    for k, body in kernels:
+        assert any("buffer_wbl2" in b for b in body), k
+        assert not _waited_before_barrier(body), k
+
+
+def test_release_check_detects_a_missing_wait():
+    body = ["\tglobal_store_dword v1, v2, s[0:1]", "\tbuffer_wbl2 sc1", "\ts_barrier", "\tglobal_store_dwordx2 v3, v[4:5], off sc1"]
+    assert _waited_before_barrier(body) == [1]
+    body.insert(2, "\ts_waitcnt vmcnt(0) expcnt(0) lgkmcnt(0)")
+    assert _waited_before_barrier(body) == []
