@@ -233,8 +233,10 @@ def bench_serve(args):
           file=sys.stderr, flush=True)
 
     def run(slots, max_jobs, rate):
+        # a launch holds at most 2^22 strings (every job here has at most
+        # 2^20), so the four slots pipeline copies, sorts and copies back
         srv = ssort.Server(0, budget_bytes=args.budget_gb << 30, slots=slots, max_jobs_per_launch=max_jobs,
-                           stage_bytes=512 << 20)
+                           stage_bytes=512 << 20, max_strings_per_launch=1 << 22)
         for j in jobs[:8]:                     # warm-up
             srv.wait(srv.submit(j))
         lat = []

@@ -231,7 +231,7 @@ struct ssort_server {
         setb[L.m] = (uint32_t)sbase;
         s.set_begin[L.m] = (uint32_t)sbase;
         s.jobs = ts;
-        pool->run(pieces.size(), [&](size_t i) { memcpy(pieces[i].dst, pieces[i].src, pieces[i].len); });
+        unlocked([&] { pool->run(pieces.size(), [&](size_t i) { memcpy(pieces[i].dst, pieces[i].src, pieces[i].len); }); });
         hipError_t ce = hipMemcpyAsync(dev, in, L.stage_in, hipMemcpyHostToDevice, s.stream);
         if (ce == hipSuccess && L.n) {
             const uint32_t grid = (uint32_t)std::min<uint64_t>((L.n + ssd::NT - 1) / ssd::NT, 4096);
@@ -257,6 +257,18 @@ struct ssort_server {
             for (uint64_t t : ts) jobs[t].status = rc;
     }
 
+    // The scheduler holds mu except while it copies between the callers'
+    // buffers and pinned staging: then submissions and waits go on.  The
+    // copies touch only the batch's own buffers (its jobs are running, so no
+    // call erases or changes them) and the slot's staging.
+    std::unique_lock<std::mutex> *held = nullptr;
+    template <typename F>
+    void unlocked(F f) {
+        if (held) held->unlock();
+        f();
+        if (held) held->lock();
+    }
+
     void complete(LaunchSlot &s, const PackLayout &L) {
         ssort_status dev_rc = ssort_query_error(s.ctx, s.stream);
         uint64_t bits = 0;
@@ -266,11 +278,18 @@ struct ssort_server {
         }
         const uint32_t *perm = s.stage_out;
         const uint32_t *lcp = (const uint32_t *)((const uint8_t *)s.stage_out + (L.lcp - L.perm));
-        pool->run(s.jobs.size(), [&](size_t k) {
+        struct Out { uint32_t *perm, *lcp; uint32_t b, n; };
+        std::vector<Out> outs(s.jobs.size());
+        for (size_t k = 0; k < s.jobs.size(); ++k) {
             const JobRec &r = jobs.at(s.jobs[k]);
-            const uint32_t b = s.set_begin[k], n = r.job.n;
-            if (r.job.out_perm) memcpy(r.job.out_perm, perm + b, 4ull * n);
-            if (r.job.out_lcp) memcpy(r.job.out_lcp, lcp + b, 4ull * n);
+            outs[k] = Out{r.job.out_perm, r.job.out_lcp, s.set_begin[k], r.job.n};
+        }
+        unlocked([&] {
+            pool->run(outs.size(), [&](size_t k) {
+                const Out &o = outs[k];
+                if (o.perm) memcpy(o.perm, perm + o.b, 4ull * o.n);
+                if (o.lcp) memcpy(o.lcp, lcp + o.b, 4ull * o.n);
+            });
         });
         const auto now = clk::now();
         for (uint32_t k = 0; k < s.jobs.size(); ++k) {
@@ -289,6 +308,7 @@ struct ssort_server {
     void loop() {
         std::vector<PackLayout> lay(slots.size());
         std::unique_lock<std::mutex> lk(mu);
+        held = &lk;
         while (!stop) {
             bool progress = false;
             for (size_t i = 0; i < slots.size(); ++i) {
@@ -357,7 +377,9 @@ ssort_status ssort_server_create(int device, size_t hbm_budget, uint32_t slots, 
         return SSORT_ENOMEM;
     }
     S->adm = new ssd::Admission(hbm_budget, 256);
-    S->pool = new CopyPool(7);
+    // host copies into and out of pinned staging bound the served throughput:
+    // 14 helpers plus the scheduler thread fill a 16-core host share
+    S->pool = new CopyPool(14);
     S->slots.resize(slots);
     for (auto &s : S->slots) {
         if (ssort_create(device, t, &s.ctx) != SSORT_OK || hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
