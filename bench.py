@@ -34,12 +34,16 @@ WORKLOAD_TEXT = {
 }
 
 
+# the files that define the sort's kernels and their launches (the merge and
+# the server are host code and kernels of their own, outside the profiled sort)
+SORT_SOURCES = ("ssort_dev.h", "ssort_kernels.h", "ssort_kernels.hip", "ssort_api.hip")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1403_2056_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in SORT_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
