@@ -304,7 +304,7 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the sorter runs on one GPU; --gpus must be 1 (sharding is described in the design notes, not implemented)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     if args.mode == "batched":
