@@ -66,8 +66,16 @@ class StringSet:
         return (self.offsets[1:] - self.offsets[:-1]).astype(np.uint64)
 
     def string(self, i: int) -> bytes:
-        s = int(self.starts()[i]) if self.n else 0
-        ln = int(self.lens()[i])
+        # One string, without building the whole start and length arrays.
+        if not 0 <= i < self.n:
+            raise IndexError(f"string {i} of {self.n}")
+        s = int(self.offsets[i])
+        if self.flags & FLAG_TO_END:
+            ln = len(self.chars) - s
+        elif self.lengths is not None:
+            ln = int(self.lengths[i])
+        else:
+            ln = int(self.offsets[i + 1]) - s
         return bytes(self.chars[s:s + ln])
 
     def strings(self) -> list[bytes]:

@@ -1,5 +1,6 @@
 """Shape checks of the seeded synthetic inputs (no method arithmetic here)."""
 import numpy as np
+import pytest
 
 from paper_1403_2056_amd import workloads as W
 
@@ -38,3 +39,20 @@ def test_batched_shape():
     assert sizes.min() >= 64 and sizes.max() <= 1024 and int(sb[-1]) == ss.n
     assert ss.lens().min() >= 1
     assert ss.chars.min() >= 0x20 and ss.chars.max() <= 0x7E
+
+
+def test_string_accessor_matches_strings():
+    # string(i) reads one string directly; it must agree with strings() on
+    # every layout, including empty strings and the suffix layout.
+    sets = [
+        W.from_list([b"ab", b"", b"abc", b"z"], "csr"),
+        W.from_list([b"ab", b"", b"abc", b"z"], "lengths", pad=3),
+        W.plain(500, seed=7),
+        W.suffixes(1 << 10, seed=3, block=256),
+    ]
+    for ss in sets:
+        strs = ss.strings()
+        assert [ss.string(i) for i in range(ss.n)] == strs
+        for bad in (-1, ss.n):
+            with pytest.raises(IndexError):
+                ss.string(bad)
