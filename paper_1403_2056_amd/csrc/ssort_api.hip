@@ -464,7 +464,17 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
     hipLaunchKernelGGL(ssm::k_mreset, dim3(1), dim3(64), 0, s, M);
     hipLaunchKernelGGL(ssm::k_mcache, dim3(grid_for(n)), dim3(NT), 0, s, M);
     hipLaunchKernelGGL(ssm::k_msample, dim3((L.nsamp + 63) / 64), dim3(64), 0, s, M);
-    hipLaunchKernelGGL(ssm::k_mmerge, dim3((L.nsamp + ssm::MNT - 1) / ssm::MNT), dim3(ssm::MNT), 0, s, M);
+    {
+        // the loser tree's LDS arrays sized for the smallest power of two >= K
+        uint32_t kp = 2;
+        while (kp < K) kp <<= 1;
+        const dim3 g((L.nsamp + ssm::MNT - 1) / ssm::MNT), b(ssm::MNT);
+        if (kp <= 2) hipLaunchKernelGGL(ssm::k_mmerge<2>, g, b, 0, s, M);
+        else if (kp == 4) hipLaunchKernelGGL(ssm::k_mmerge<4>, g, b, 0, s, M);
+        else if (kp == 8) hipLaunchKernelGGL(ssm::k_mmerge<8>, g, b, 0, s, M);
+        else if (kp == 16) hipLaunchKernelGGL(ssm::k_mmerge<16>, g, b, 0, s, M);
+        else hipLaunchKernelGGL(ssm::k_mmerge<ssm::MKMAX>, g, b, 0, s, M);
+    }
     if (out_lcp) hipLaunchKernelGGL(ssm::k_mseam, dim3((L.nsamp + 63) / 64), dim3(64), 0, s, M);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;

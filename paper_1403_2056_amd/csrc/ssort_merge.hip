@@ -138,12 +138,16 @@ __global__ void k_msample(MergeParams M) {
 
 // Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run,
 // its LCP with the winner of that game, and its 8 characters at that LCP.
+// KM, a power of two >= K, sizes the arrays: 24 * KM bytes per thread, so a
+// tree sized for the launch's K (not the largest) keeps more workgroups
+// resident per CU.
+template <int KM>
 struct MergeLDS {
-    uint32_t y[MKMAX][MNT];
-    uint32_t h[MKMAX][MNT];
-    uint64_t c[MKMAX][MNT];
-    uint32_t pos[MKMAX][MNT];   // next element of each run (absolute)
-    uint32_t end[MKMAX][MNT];
+    uint32_t y[KM][MNT];
+    uint32_t h[KM][MNT];
+    uint64_t c[KM][MNT];
+    uint32_t pos[KM][MNT];   // next element of each run (absolute)
+    uint32_t end[KM][MNT];
 };
 
 // One game (Algorithm 2 with cached characters): the candidate (x, hx, cx)
@@ -193,14 +197,19 @@ __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t 
     return x_less;
 }
 
+template <int KM>
 __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
-    __shared__ MergeLDS L;
+    __shared__ MergeLDS<KM> L;
     const uint32_t j = blockIdx.x * MNT + threadIdx.x;
     if (j >= M.nsamp || *M.err) return;
     const int me = threadIdx.x;
     const uint32_t K = M.K;
     uint32_t KP = 1;
     while (KP < K) KP <<= 1;
+    if (KP > (uint32_t)KM) {   // the host picked a tree too small for K
+        atomicOr(M.err, ssd::ERR_MERGE);
+        return;
+    }
     // this job: for each run, the elements between cut rows j and j+1
     uint32_t out = 0;
     for (uint32_t r = 0; r < KP; ++r) {
@@ -217,9 +226,9 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     // players: the runs' first elements of the job, LCP 0 against the empty
     // string; the tree is built bottom-up with the winners of subtrees kept
     // in the leaf slots' place (node v < KP holds a loser, win[] the winner)
-    uint32_t wrun[MKMAX];
-    uint32_t wh[MKMAX];
-    uint64_t wc[MKMAX];
+    uint32_t wrun[KM];
+    uint32_t wh[KM];
+    uint64_t wc[KM];
     auto player = [&](uint32_t r, uint32_t *id) -> bool {
         if (r >= K || L.pos[r][me] >= L.end[r][me]) return false;
         *id = M.pin[L.pos[r][me]];
