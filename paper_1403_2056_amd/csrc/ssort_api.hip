@@ -390,7 +390,7 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
 
 // ---- K-way LCP-merge ----
 namespace {
-constexpr uint32_t MERGE_G = 256;   // sample spacing: jobs of about K * 128 strings on average
+constexpr uint32_t MERGE_G = 128;   // sample spacing: n / MERGE_G jobs of about MERGE_G strings each
 
 struct MergeLayout {
     size_t ctl, cache, cuts, total;
