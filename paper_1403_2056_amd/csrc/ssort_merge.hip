@@ -136,14 +136,17 @@ __global__ void k_msample(MergeParams M) {
     for (uint32_t r = 0; r < M.K; ++r) M.cuts[(size_t)order * M.K + r] = cut[r];
 }
 
-// Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run,
-// its LCP with the winner of that game, and its 8 characters at that LCP.
-// KM, a power of two >= K, sizes the arrays: 24 * KM bytes per thread, so a
+// Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run, its
+// string id, its LCP with the winner of that game, and its 8 characters at
+// that LCP.  A loser's run does not advance while it sits in the tree, so the
+// id stays valid there and the replay reads no run position from global
+// memory.  KM, a power of two >= K, sizes the arrays: 28 * KM bytes per thread, so a
 // tree sized for the launch's K (not the largest) keeps more workgroups
 // resident per CU.
 template <int KM>
 struct MergeLDS {
     uint32_t y[KM][MNT];
+    uint32_t yi[KM][MNT];   // string id of the loser's current element
     uint32_t h[KM][MNT];
     uint64_t c[KM][MNT];
     uint32_t pos[KM][MNT];   // next element of each run (absolute)
@@ -260,6 +263,7 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             const bool aw = game(M, a, aid, wh[2 * q], wc[2 * q], b, bid, wh[2 * q + 1], wc[2 * q + 1], &lh, &lc);
             const uint32_t v = (base >> 1) + q;   // node index of this game
             L.y[v][me] = aw ? b : a;
+            L.yi[v][me] = aw ? bid : aid;
             L.h[v][me] = lh;
             L.c[v][me] = lc;
             const uint32_t wr = aw ? a : b;
@@ -293,12 +297,13 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         }
         for (uint32_t v = (KP + w) >> 1; v >= 1; v >>= 1) {
             const uint32_t y = L.y[v][me];
-            const uint32_t yid = y == SENT ? 0u : M.pin[L.pos[y][me]];
+            const uint32_t yid = L.yi[v][me];
             uint32_t lh;
             uint64_t lc;
             const bool xw = game(M, x, xid, hx, cx, y, yid, L.h[v][me], L.c[v][me], &lh, &lc);
             if (!xw) {
                 L.y[v][me] = x;
+                L.yi[v][me] = xid;
                 x = y;
                 xid = yid;
                 hx = L.h[v][me];
