@@ -62,7 +62,7 @@ def merge_parity(sorter, ss, K, seed, label, contiguous=False):
         raise AssertionError(f"{label}: lcp differs at {bad}: {h[bad]} vs {rh[bad]}")
 
 
-@pytest.mark.parametrize("K", [1, 2, 3, 8, 32])
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 8, 12, 32])
 def test_merge_plain(sorter, K):
     merge_parity(sorter, W.plain(60000, seed=60 + K), K, K, f"plain K={K}")
 
