@@ -463,7 +463,12 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
     M.nsamp = L.nsamp;
     hipLaunchKernelGGL(ssm::k_mreset, dim3(1), dim3(64), 0, s, M);
     hipLaunchKernelGGL(ssm::k_mcache, dim3(grid_for(n)), dim3(NT), 0, s, M);
-    hipLaunchKernelGGL(ssm::k_msample, dim3((L.nsamp + 63) / 64), dim3(64), 0, s, M);
+    {
+        // KP lanes per sample (KP: the smallest power of two >= K, at most 32)
+        uint32_t kps = 1;
+        while (kps < K) kps <<= 1;
+        hipLaunchKernelGGL(ssm::k_msample, dim3((uint32_t)(((size_t)L.nsamp * kps + 63) / 64)), dim3(64), 0, s, M);
+    }
     {
         // the loser tree's LDS arrays sized for the smallest power of two >= K
         uint32_t kp = 2;

@@ -85,28 +85,40 @@ __global__ void k_mcache(MergeParams M) {
 // Number of samples of run k below position c (samples sit at 0, g, 2g, ...).
 __device__ __forceinline__ uint32_t samples_below(uint32_t c, uint32_t g) { return (c + g - 1) / g; }
 
-// One thread per sample: its cut in every run (lower bound of (string, index)
-// with the LCP-accelerated binary search: the search keeps the LCPs of the
-// sample with the elements just outside [lo, hi) and compares from their
-// minimum), and its position in sample order.
+// One lane per (sample, run): the lanes of a sample form a group of KP, the
+// smallest power of two >= K, aligned inside the 64-wide wavefront.  Lane r
+// finds the sample's cut in run r (lower bound of (string, index) with the
+// LCP-accelerated binary search: the search keeps the LCPs of the sample with
+// the elements just outside [lo, hi) and compares from their minimum); the
+// group sums the samples below the cuts by shuffles into the sample's
+// position in sample order, and lane r writes cut r of that row.
 __global__ void k_msample(MergeParams M) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= M.nsamp || *M.err) return;
+    if (*M.err) return;
+    uint32_t KP = 1;
+    while (KP < M.K) KP <<= 1;
+    const uint32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t t = gt / KP;   // sample
+    const uint32_t r = gt % KP;   // run this lane searches
     // which run and position: samples of run k are numbered from the
     // running total of earlier runs' samples
-    uint32_t k = 0, base = 0;
-    for (; k < M.K; ++k) {
-        const uint32_t c = samples_below(M.rb[k + 1] - M.rb[k], M.g);
-        if (t < base + c) break;
-        base += c;
+    bool live = t < M.nsamp;
+    uint32_t k = 0, pos = 0, sid = 0;
+    if (live) {
+        uint32_t base = 0;
+        for (; k < M.K; ++k) {
+            const uint32_t c = samples_below(M.rb[k + 1] - M.rb[k], M.g);
+            if (t < base + c) break;
+            base += c;
+        }
+        live = k < M.K;
+        if (live) {
+            pos = (t - base) * M.g;
+            sid = M.pin[M.rb[k] + pos];
+        }
     }
-    if (k >= M.K) return;
-    const uint32_t pos = (t - base) * M.g;
-    const uint32_t sid = M.pin[M.rb[k] + pos];
-    uint32_t order = 0;
-    uint32_t cut[MKMAX];
-    for (uint32_t r = 0; r < M.K; ++r) {
-        uint32_t c;
+    const bool mine = live && r < M.K;
+    uint32_t c = 0;
+    if (mine) {
         if (r == k) {
             c = pos;
         } else {
@@ -126,14 +138,15 @@ __global__ void k_msample(MergeParams M) {
             }
             c = lo;
         }
-        cut[r] = c;
-        order += samples_below(c, M.g);
     }
+    uint32_t order = mine ? samples_below(c, M.g) : 0u;
+    for (uint32_t o = 1; o < KP; o <<= 1) order += (uint32_t)__shfl_xor((int)order, (int)o, 64);
+    if (!mine) return;
     if (order >= M.nsamp) {
         atomicOr(M.err, ssd::ERR_MERGE);
         return;
     }
-    for (uint32_t r = 0; r < M.K; ++r) M.cuts[(size_t)order * M.K + r] = cut[r];
+    M.cuts[(size_t)order * M.K + r] = c;
 }
 
 // Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run, its
