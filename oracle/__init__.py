@@ -25,7 +25,7 @@ u64p = ctypes.POINTER(ctypes.c_uint64)
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-pthread", "-shared", "-fPIC",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -39,7 +39,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.ssort_oracle_sort.restype = ctypes.c_int
         L.ssort_oracle_sort.argtypes = [u8p, ctypes.c_uint64, u64p, u32p, ctypes.c_uint32,
-                                        ctypes.c_uint32, u32p, u32p]
+                                        ctypes.c_uint32, u32p, u32p, ctypes.c_int]
         L.ssort_oracle_stats.restype = ctypes.c_int
         L.ssort_oracle_stats.argtypes = [u8p, ctypes.c_uint64, u64p, u32p, ctypes.c_uint32,
                                          ctypes.c_uint32, u32p, u32p, u64p]
@@ -55,6 +55,16 @@ def lib():
         L.ssort_oracle_tree_ranks.argtypes = [ctypes.c_uint32, u32p]
         L.ssort_oracle_splitter_lcp.restype = None
         L.ssort_oracle_splitter_lcp.argtypes = [u64p, ctypes.c_uint32, u32p]
+        L.ssort_oracle_lcp_insertion_sort.restype = ctypes.c_int
+        L.ssort_oracle_lcp_insertion_sort.argtypes = [u8p, ctypes.c_uint64, u64p, u32p, ctypes.c_uint32,
+                                                      ctypes.c_uint32, u32p, ctypes.c_uint32, ctypes.c_uint32,
+                                                      u32p, u32p, u64p]
+        L.ssort_oracle_lcp_merge.restype = ctypes.c_int
+        L.ssort_oracle_lcp_merge.argtypes = [u8p, ctypes.c_uint64, u64p, u32p, ctypes.c_uint32, ctypes.c_uint32,
+                                             u32p, ctypes.c_uint32, ctypes.c_int, u32p, u32p, u32p, u32p, u64p]
+        L.ssort_oracle_lcp_mergesort.restype = ctypes.c_int
+        L.ssort_oracle_lcp_mergesort.argtypes = [u8p, ctypes.c_uint64, u64p, u32p, ctypes.c_uint32,
+                                                 ctypes.c_uint32, ctypes.c_uint32, u32p, u32p, u64p]
         _lib = L
     return _lib
 
@@ -78,12 +88,15 @@ def _args(ss):
                   ctypes.c_uint32(ss.n), ctypes.c_uint32(ss.flags)]
 
 
-def sort(ss, with_lcp: bool = True):
-    """(perm, lcp) as uint32 arrays; lcp is None when with_lcp is False."""
+def sort(ss, with_lcp: bool = True, threads: int = 1):
+    """(perm, lcp) as uint32 arrays; lcp is None when with_lcp is False.
+    threads > 1 runs the same multikey quicksort on that many host threads
+    (a shared job queue for subproblems above 2^16 strings); the result is
+    the same."""
     keep, a = _args(ss)
     perm = np.empty(max(ss.n, 1), dtype=np.uint32)
     lcp = np.empty(max(ss.n, 1), dtype=np.uint32) if with_lcp else None
-    rc = lib().ssort_oracle_sort(*a, _p(perm, u32p), _p(lcp, u32p))
+    rc = lib().ssort_oracle_sort(*a, _p(perm, u32p), _p(lcp, u32p), ctypes.c_int(threads))
     if rc != 0:
         raise ValueError(f"oracle rejected input (rc={rc})")
     del keep
@@ -149,3 +162,57 @@ def splitter_lcp(splitters: np.ndarray) -> np.ndarray:
     out = np.zeros(x.size + 1, dtype=np.uint32)
     lib().ssort_oracle_splitter_lcp(_p(x, u64p), ctypes.c_uint32(x.size), _p(out, u32p))
     return out
+
+
+def lcp_insertion_sort(ss, idx, hbar: int = 0):
+    """Algorithm 5 on the strings idx (which share the prefix hbar): (perm,
+    lcp, character comparisons)."""
+    keep, a = _args(ss)
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    m = idx.size
+    perm = np.zeros(max(m, 1), dtype=np.uint32)
+    lcp = np.zeros(max(m, 1), dtype=np.uint32)
+    cnt = np.zeros(1, dtype=np.uint64)
+    rc = lib().ssort_oracle_lcp_insertion_sort(*a, _p(idx, u32p), ctypes.c_uint32(m), ctypes.c_uint32(hbar),
+                                               _p(perm, u32p), _p(lcp, u32p), _p(cnt, u64p))
+    if rc != 0:
+        raise ValueError(f"oracle rejected input (rc={rc})")
+    del keep
+    return perm[:m], lcp[:m], int(cnt[0])
+
+
+def lcp_merge(ss, run_begin, perm_in, lcp_in, binary: bool = False):
+    """K-way LCP-merge (Algorithm 4; Algorithm 3 with binary and K = 2) of
+    sorted runs: (perm, lcp, character comparisons)."""
+    keep, a = _args(ss)
+    rb = np.ascontiguousarray(run_begin, dtype=np.uint32)
+    K = rb.size - 1
+    pin = np.ascontiguousarray(perm_in, dtype=np.uint32)
+    hin = np.ascontiguousarray(lcp_in, dtype=np.uint32)
+    n = int(rb[-1])
+    if pin.size == 0:
+        pin = np.zeros(1, np.uint32)
+        hin = np.zeros(1, np.uint32)
+    perm = np.zeros(max(n, 1), dtype=np.uint32)
+    lcp = np.zeros(max(n, 1), dtype=np.uint32)
+    cnt = np.zeros(1, dtype=np.uint64)
+    rc = lib().ssort_oracle_lcp_merge(*a, _p(rb, u32p), ctypes.c_uint32(K), ctypes.c_int(1 if binary else 0),
+                                      _p(pin, u32p), _p(hin, u32p), _p(perm, u32p), _p(lcp, u32p), _p(cnt, u64p))
+    if rc != 0:
+        raise ValueError(f"oracle rejected input (rc={rc})")
+    del keep
+    return perm[:n], lcp[:n], int(cnt[0])
+
+
+def lcp_mergesort(ss, K: int = 2):
+    """LCP-mergesort (binary with K = 2, else K-way): (perm, lcp, character
+    comparisons)."""
+    keep, a = _args(ss)
+    perm = np.zeros(max(ss.n, 1), dtype=np.uint32)
+    lcp = np.zeros(max(ss.n, 1), dtype=np.uint32)
+    cnt = np.zeros(1, dtype=np.uint64)
+    rc = lib().ssort_oracle_lcp_mergesort(*a, ctypes.c_uint32(K), _p(perm, u32p), _p(lcp, u32p), _p(cnt, u64p))
+    if rc != 0:
+        raise ValueError(f"oracle rejected input (rc={rc})")
+    del keep
+    return perm[:ss.n], lcp[:ss.n], int(cnt[0])

@@ -18,12 +18,27 @@
  * at d and on "=" at d+1, and an insertion sort for small ranges.  The LCP
  * array is the plain definition, a byte loop over adjacent outputs.
  *
- * The single-step helpers at the end restate one step of super scalar string
- * sample sort (Algorithm 1, Fig. 1, Implementation details) in its plain
- * form: the 8-byte big-endian key with zero padding, the lower-bound bucket
- * number with equality buckets, the level order of a perfect search tree, and
- * the splitter LCPs by a byte loop.  They check intermediate results.
+ * With threads > 1 the same sequential multikey quicksort runs on several
+ * threads: a subproblem of more than 2^16 strings goes to a shared job queue
+ * guarded by a mutex instead of the thread's own stack (the job-queue pattern
+ * of the practical parallelisation of S5, Section 4.5).  The subproblems are
+ * disjoint ranges and each is partitioned deterministically, so the result
+ * does not depend on the thread count or the schedule.  This exists to time
+ * the oracle on every host core; it is the same algorithm.
+ *
+ * The single-step helpers restate one step of super scalar string sample sort
+ * (Algorithm 1, Fig. 1, Implementation details) in its plain form: the 8-byte
+ * big-endian key with zero padding, the lower-bound bucket number with
+ * equality buckets, the level order of a perfect search tree, and the
+ * splitter LCPs by a byte loop.  They check intermediate results.
+ *
+ * The LCP algorithms of Section 5 at the end (LCP-insertion sort, Algorithm
+ * 5; binary LCP-compare and LCP-merge, Algorithms 2 and 3; K-way LCP-merge
+ * with an LCP-aware tournament tree, Algorithm 4) are written out with a
+ * counter of character comparisons, so that the tests can hold them to the
+ * bounds of the section's theorems and to the plain definition above.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -88,11 +103,44 @@ static int cmp_u32(const void *x, const void *y)
 
 typedef struct { uint64_t lo, hi, d; } frame_t;
 
-static void mkqs(const strs_t *S, uint32_t *a, uint64_t n)
+/* Shared job queue of the multi-threaded run (NULL: one thread). */
+#define POOL_SPLIT (1u << 16)
+typedef struct {
+    pthread_mutex_t mu;
+    pthread_cond_t cv;
+    frame_t *q;
+    uint64_t qn, qcap;
+    int active;          /* threads working on a job */
+    int failed;          /* an allocation failed */
+} pool_t;
+
+static void pool_push(pool_t *P, frame_t f)
+{
+    pthread_mutex_lock(&P->mu);
+    if (P->qn == P->qcap) {
+        uint64_t nc = P->qcap ? 2 * P->qcap : 64;
+        frame_t *nq = (frame_t *)realloc(P->q, sizeof(frame_t) * nc);
+        if (!nq) {
+            P->failed = 1;
+            pthread_mutex_unlock(&P->mu);
+            return;
+        }
+        P->q = nq;
+        P->qcap = nc;
+    }
+    P->q[P->qn++] = f;
+    pthread_cond_signal(&P->cv);
+    pthread_mutex_unlock(&P->mu);
+}
+
+/* Multikey quicksort of the frame f with the thread's own stack; frames of
+ * more than POOL_SPLIT strings go to the shared queue when there is one. */
+static int mkqs_frame(const strs_t *S, uint32_t *a, frame_t f0, pool_t *pool)
 {
     uint64_t cap = 1024, top = 0;
     frame_t *stk = (frame_t *)malloc(sizeof(frame_t) * cap);
-    stk[top++] = (frame_t){0, n, 0};
+    if (!stk) return -1;
+    stk[top++] = f0;
     while (top) {
         frame_t f = stk[--top];
         uint64_t m = f.hi - f.lo;
@@ -127,17 +175,84 @@ static void mkqs(const strs_t *S, uint32_t *a, uint64_t n)
             }
         }
         if (top + 3 > cap) {
+            frame_t *grown = (frame_t *)realloc(stk, sizeof(frame_t) * cap * 2);
+            if (!grown) {
+                free(stk);
+                return -1;
+            }
+            stk = grown;
             cap *= 2;
-            stk = (frame_t *)realloc(stk, sizeof(frame_t) * cap);
         }
-        stk[top++] = (frame_t){f.lo, lt, f.d};
-        stk[top++] = (frame_t){gt, f.hi, f.d};
+        frame_t sub[3];
+        int ns = 0;
+        sub[ns++] = (frame_t){f.lo, lt, f.d};
+        sub[ns++] = (frame_t){gt, f.hi, f.d};
         if (pv == 0)        /* every string of the "=" group ended: identical strings */
             qsort(a + lt, gt - lt, sizeof(uint32_t), cmp_u32);
         else
-            stk[top++] = (frame_t){lt, gt, f.d + 1};
+            sub[ns++] = (frame_t){lt, gt, f.d + 1};
+        for (int k = 0; k < ns; ++k) {
+            if (pool && sub[k].hi - sub[k].lo > POOL_SPLIT) pool_push(pool, sub[k]);
+            else stk[top++] = sub[k];
+        }
     }
     free(stk);
+    return 0;
+}
+
+typedef struct {
+    const strs_t *S;
+    uint32_t *a;
+    pool_t *pool;
+} worker_arg_t;
+
+/* A thread of the multi-threaded run: take jobs until the queue is empty and
+ * no other thread can add one. */
+static void *pool_worker(void *arg)
+{
+    worker_arg_t *W = (worker_arg_t *)arg;
+    pool_t *P = W->pool;
+    for (;;) {
+        pthread_mutex_lock(&P->mu);
+        while (P->qn == 0 && P->active > 0) pthread_cond_wait(&P->cv, &P->mu);
+        if (P->qn == 0) {
+            pthread_cond_broadcast(&P->cv);
+            pthread_mutex_unlock(&P->mu);
+            return NULL;
+        }
+        frame_t f = P->q[--P->qn];
+        P->active++;
+        pthread_mutex_unlock(&P->mu);
+        int rc = mkqs_frame(W->S, W->a, f, P);
+        pthread_mutex_lock(&P->mu);
+        if (rc) P->failed = 1;
+        P->active--;
+        if (P->qn == 0 && P->active == 0) pthread_cond_broadcast(&P->cv);
+        pthread_mutex_unlock(&P->mu);
+    }
+}
+
+static int mkqs(const strs_t *S, uint32_t *a, uint64_t n, int threads)
+{
+    if (threads <= 1 || n <= POOL_SPLIT) return mkqs_frame(S, a, (frame_t){0, n, 0}, NULL);
+    pool_t P;
+    memset(&P, 0, sizeof(P));
+    pthread_mutex_init(&P.mu, NULL);
+    pthread_cond_init(&P.cv, NULL);
+    pool_push(&P, (frame_t){0, n, 0});
+    worker_arg_t W = {S, a, &P};
+    pthread_t *tid = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)threads);
+    int started = 0;
+    if (tid)
+        for (int t = 1; t < threads; ++t)
+            if (pthread_create(&tid[started], NULL, pool_worker, &W) == 0) ++started;
+    pool_worker(&W);
+    for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    free(tid);
+    free(P.q);
+    pthread_cond_destroy(&P.cv);
+    pthread_mutex_destroy(&P.mu);
+    return P.failed ? -1 : 0;
 }
 
 static uint64_t lcp_pair(const strs_t *S, uint32_t a, uint32_t b)
@@ -149,21 +264,61 @@ static uint64_t lcp_pair(const strs_t *S, uint32_t a, uint32_t b)
     return h;
 }
 
-/* Sort; perm and lcp (nullable) are host arrays of n entries.  Returns 0 on
- * success, <0 on bad input.  lcp values are clamped to 32 bits (strings longer
+typedef struct {
+    const strs_t *S;
+    const uint32_t *perm;
+    uint32_t *lcp;
+    uint32_t lo, hi;
+} lcp_arg_t;
+
+static void *lcp_range(void *arg)
+{
+    lcp_arg_t *A = (lcp_arg_t *)arg;
+    for (uint32_t i = A->lo; i < A->hi; ++i)
+        A->lcp[i] = i ? (uint32_t)lcp_pair(A->S, A->perm[i - 1], A->perm[i]) : 0;
+    return NULL;
+}
+
+/* Sort; perm and lcp (nullable) are host arrays of n entries; threads <= 1
+ * runs on the calling thread only.  Returns 0 on success, <0 on bad input
+ * (-1: out of memory).  lcp values are clamped to 32 bits (strings longer
  * than 4 GiB are outside the library's contract). */
 int ssort_oracle_sort(const uint8_t *chars, uint64_t nchars, const uint64_t *offsets,
                       const uint32_t *lengths, uint32_t n, uint32_t flags,
-                      uint32_t *perm, uint32_t *lcp)
+                      uint32_t *perm, uint32_t *lcp, int threads)
 {
     strs_t S;
     int rc = load_strs(&S, chars, nchars, offsets, lengths, n, flags);
     if (rc) { free_strs(&S); return rc; }
     for (uint32_t i = 0; i < n; ++i) perm[i] = i;
-    mkqs(&S, perm, n);
+    if (mkqs(&S, perm, n, threads)) { free_strs(&S); return -1; }
     if (lcp) {
-        if (n) lcp[0] = 0;
-        for (uint32_t i = 1; i < n; ++i) lcp[i] = (uint32_t)lcp_pair(&S, perm[i - 1], perm[i]);
+        /* the LCP array: the byte loop over neighbours, in ranges per thread */
+        int T = threads > 1 ? threads : 1;
+        if ((uint64_t)T > (uint64_t)n / 65536 + 1) T = (int)((uint64_t)n / 65536 + 1);
+        lcp_arg_t *A = (lcp_arg_t *)malloc(sizeof(lcp_arg_t) * (size_t)T);
+        pthread_t *tid = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)T);
+        if (!A || !tid) {
+            free(A);
+            free(tid);
+            free_strs(&S);
+            return -1;
+        }
+        /* thread t > 0 computes range t; a thread that cannot start leaves
+         * its range to the calling thread */
+        uint8_t *run = (uint8_t *)calloc((size_t)T, 1);
+        for (int t = 0; t < T; ++t)
+            A[t] = (lcp_arg_t){&S, perm, lcp, (uint32_t)((uint64_t)n * t / T), (uint32_t)((uint64_t)n * (t + 1) / T)};
+        for (int t = 1; t < T; ++t)
+            if (run && pthread_create(&tid[t], NULL, lcp_range, &A[t]) == 0) run[t] = 1;
+        lcp_range(&A[0]);
+        for (int t = 1; t < T; ++t) {
+            if (run && run[t]) pthread_join(tid[t], NULL);
+            else lcp_range(&A[t]);
+        }
+        free(run);
+        free(A);
+        free(tid);
     }
     free_strs(&S);
     return 0;
@@ -295,4 +450,284 @@ void ssort_oracle_splitter_lcp(const uint64_t *x, uint32_t v, uint32_t *h)
         while (l < 8 && ((x[i - 1] >> (56 - 8 * l)) & 0xFF) == ((x[i] >> (56 - 8 * l)) & 0xFF)) ++l;
         h[i] = l;
     }
+}
+
+/* ---- Section 5: LCP-aware insertion sort and merging, with a counter of
+ * character comparisons.  A character comparison is one evaluation of the
+ * loop condition that compares the characters of two strings at the same
+ * position (the final ordering test after the loop uses the same two
+ * characters and is counted with the comparison that ended the loop, as the
+ * proofs of the section do). ---- */
+
+/* LCP-insertion sort (Algorithm 5) of the strings idx[0..m), which share the
+ * common prefix hbar.  out_perm gets the sorted order (identical strings keep
+ * their order in idx: x is placed after an equal string), out_lcp the LCP
+ * array (out_lcp[0] = 0).  *ncmp counts character comparisons (bounded by
+ * L + m(m-1)/2 by the theorem after Algorithm 5).  Returns 0, or <0 on bad
+ * input. */
+int ssort_oracle_lcp_insertion_sort(const uint8_t *chars, uint64_t nchars, const uint64_t *offsets,
+                                    const uint32_t *lengths, uint32_t n, uint32_t flags,
+                                    const uint32_t *idx, uint32_t m, uint32_t hbar,
+                                    uint32_t *out_perm, uint32_t *out_lcp, uint64_t *ncmp)
+{
+    strs_t S;
+    int rc = load_strs(&S, chars, nchars, offsets, lengths, n, flags);
+    if (rc) { free_strs(&S); return rc; }
+    for (uint32_t j = 0; j < m; ++j)
+        if (idx[j] >= n) { free_strs(&S); return -3; }
+    /* s[0..j) sorted, H[i] = lcp(s[i-1], s[i]) for 1 <= i < j */
+    uint32_t *s = out_perm;
+    uint64_t *H = (uint64_t *)calloc((size_t)m + 1, sizeof(uint64_t));
+    if (!H) { free_strs(&S); return -1; }
+    uint64_t cnt = 0;
+    for (uint32_t j = 0; j < m; ++j) {
+        uint32_t x = idx[j];
+        uint64_t hp = hbar;          /* h': LCP of x with the string last passed */
+        uint64_t i = j;
+        H[j] = hbar;                 /* x shares hbar with every string */
+        while (i > 0) {
+            if (H[i] < hp) break;                   /* case 1: s[i-1] < x */
+            if (H[i] == hp) {                       /* case 2: compare characters */
+                uint64_t p = hp;
+                for (;;) {
+                    ++cnt;
+                    int cx = ch(&S, x, hp), cy = ch(&S, s[i - 1], hp);
+                    if (!(cx != 0 && cx == cy)) break;
+                    ++hp;
+                }
+                if (ch(&S, x, hp) >= ch(&S, s[i - 1], hp)) {   /* x after s[i-1] */
+                    H[i] = hp;
+                    hp = p;
+                    break;
+                }
+            }
+            /* case 3 (or x smaller after comparing): move s[i-1] right */
+            s[i] = s[i - 1];
+            H[i + 1] = H[i];
+            --i;
+        }
+        s[i] = x;
+        H[i + 1] = hp;
+    }
+    if (out_lcp) {
+        if (m) out_lcp[0] = 0;
+        for (uint32_t i = 1; i < m; ++i) out_lcp[i] = (uint32_t)H[i];
+    }
+    if (ncmp) *ncmp = cnt;
+    free(H);
+    free_strs(&S);
+    return 0;
+}
+
+/* Binary LCP-compare (Algorithm 2) of strings a and b with ha = lcp(p, s_a),
+ * hb = lcp(p, s_b) for a common smaller string p.  Returns 1 when s_a comes
+ * first (equal strings: the smaller input index first, the stable reading of
+ * the algorithm's "a for s_a <= s_b"); *h gets lcp(s_a, s_b). */
+static int lcp_compare(const strs_t *S, uint32_t a, uint64_t ha, uint32_t b, uint64_t hb, uint64_t *h, uint64_t *cnt)
+{
+    if (ha == hb) {                                  /* case 1 */
+        uint64_t hh = ha;
+        for (;;) {
+            ++*cnt;
+            int ca = ch(S, a, hh), cb = ch(S, b, hh);
+            if (!(ca != 0 && ca == cb)) break;
+            ++hh;
+        }
+        *h = hh;
+        int ca = ch(S, a, hh), cb = ch(S, b, hh);
+        if (ca != cb) return ca < cb;
+        return a < b;                                /* both ended: identical strings */
+    }
+    if (ha < hb) {                                   /* case 2: s_b first */
+        *h = ha;
+        return 0;
+    }
+    *h = hb;                                         /* case 3: s_a first */
+    return 1;
+}
+
+/* K-way LCP-merge (Algorithm 4) of the runs [rb[k], rb[k+1]) of (perm, lcp)
+ * into (out_perm, out_lcp), with an LCP-aware loser tree over KP leaves (KP
+ * the smallest power of two >= K; the extra leaves are empty runs). */
+static int kway_merge(const strs_t *S, const uint32_t *rb, uint32_t K, const uint32_t *perm, const uint32_t *lcp,
+                      uint32_t *out_perm, uint32_t *out_lcp, uint64_t *cnt)
+{
+    uint32_t KP = 1;
+    while (KP < K) KP <<= 1;
+    const uint32_t NONE = 0xFFFFFFFFu;   /* an exhausted run (the sentinel, larger than every string) */
+    uint64_t *pos = (uint64_t *)malloc(sizeof(uint64_t) * KP);
+    uint32_t *y = (uint32_t *)malloc(sizeof(uint32_t) * 2 * KP);    /* loser run of each game node */
+    uint64_t *hy = (uint64_t *)malloc(sizeof(uint64_t) * 2 * KP);   /* its LCP with that game's winner */
+    if (!pos || !y || !hy) { free(pos); free(y); free(hy); return -1; }
+    for (uint32_t r = 0; r < KP; ++r) pos[r] = r < K ? rb[r] : 0;
+    #define RUN_LIVE(r) ((r) != NONE && (r) < K && pos[r] < rb[(r) + 1])
+    /* initial games bottom-up: node v's winner passes up, its loser stays;
+     * wn/wh hold the winners of the level below */
+    uint32_t *wn = (uint32_t *)malloc(sizeof(uint32_t) * 2 * KP);
+    uint64_t *wh = (uint64_t *)malloc(sizeof(uint64_t) * 2 * KP);
+    if (!wn || !wh) { free(pos); free(y); free(hy); free(wn); free(wh); return -1; }
+    for (uint32_t r = 0; r < KP; ++r) {
+        wn[KP + r] = RUN_LIVE(r) ? r : NONE;
+        wh[KP + r] = 0;              /* LCP with the empty string */
+    }
+    for (uint32_t v = KP - 1; v >= 1; --v) {
+        uint32_t a = wn[2 * v], b = wn[2 * v + 1];
+        uint64_t ha = wh[2 * v], hb = wh[2 * v + 1];
+        if (b == NONE) { wn[v] = a; wh[v] = ha; y[v] = b; hy[v] = hb; continue; }
+        if (a == NONE) { wn[v] = b; wh[v] = hb; y[v] = a; hy[v] = ha; continue; }
+        uint64_t h;
+        int af = lcp_compare(S, perm[pos[a]], ha, perm[pos[b]], hb, &h, cnt);
+        wn[v] = af ? a : b;
+        wh[v] = af ? ha : hb;
+        y[v] = af ? b : a;
+        hy[v] = h;
+    }
+    uint32_t w = KP > 1 ? wn[1] : wn[KP];
+    uint64_t hw = KP > 1 ? wh[1] : wh[KP];
+    uint64_t j = 0;
+    while (w != NONE) {
+        out_perm[j] = perm[pos[w]];
+        if (out_lcp) out_lcp[j] = j ? (uint32_t)hw : 0;
+        ++j;
+        /* the winner's run advances; its next string's LCP with the string
+         * just written is the run's own LCP entry */
+        ++pos[w];
+        uint32_t x = RUN_LIVE(w) ? w : NONE;
+        uint64_t hx = x != NONE ? lcp[pos[w]] : 0;
+        for (uint32_t v = (KP + w) >> 1; v >= 1; v >>= 1) {
+            uint32_t b = y[v];
+            if (b == NONE) continue;                 /* x wins against an empty run */
+            if (x == NONE) {                         /* the stored loser wins */
+                y[v] = x; x = b;
+                uint64_t t = hy[v]; hy[v] = hx; hx = t;
+                continue;
+            }
+            uint64_t h;
+            int xf = lcp_compare(S, perm[pos[x]], hx, perm[pos[b]], hy[v], &h, cnt);
+            if (!xf) {
+                y[v] = x;
+                x = b;
+                hx = hy[v];
+            }
+            hy[v] = h;
+        }
+        w = x;
+        hw = hx;
+    }
+    #undef RUN_LIVE
+    free(pos); free(y); free(hy); free(wn); free(wh);
+    return 0;
+}
+
+/* Binary LCP-merge (Algorithm 3) of two runs of (perm, lcp). */
+static void binary_merge(const strs_t *S, const uint32_t *pa, const uint32_t *la, uint64_t na,
+                         const uint32_t *pb, const uint32_t *lb, uint64_t nb,
+                         uint32_t *out_perm, uint32_t *out_lcp, uint64_t *cnt)
+{
+    uint64_t i = 0, k = 0, j = 0;
+    uint64_t ha = 0, hb = 0;     /* LCPs of the candidates with the last output (first: the empty string) */
+    while (i < na && k < nb) {
+        uint64_t h;
+        int af = lcp_compare(S, pa[i], ha, pb[k], hb, &h, cnt);
+        if (af) {
+            out_perm[j] = pa[i];
+            out_lcp[j++] = (uint32_t)ha;
+            ++i;
+            hb = h;                               /* lcp(written s_a, s_b) */
+            ha = i < na ? la[i] : 0;              /* lcp(written s_a, its successor) */
+        } else {
+            out_perm[j] = pb[k];
+            out_lcp[j++] = (uint32_t)hb;
+            ++k;
+            ha = h;
+            hb = k < nb ? lb[k] : 0;
+        }
+    }
+    for (; i < na; ++i, ha = i < na ? la[i] : 0) { out_perm[j] = pa[i]; out_lcp[j++] = (uint32_t)ha; }
+    for (; k < nb; ++k, hb = k < nb ? lb[k] : 0) { out_perm[j] = pb[k]; out_lcp[j++] = (uint32_t)hb; }
+}
+
+/* Merge K sorted runs of indices into `in` (Algorithm 4; with binary != 0 and
+ * K = 2, Algorithm 3).  run_begin[0..K]; lcp_in[p] = LCP of the strings at
+ * p-1 and p of the same run (ignored at a run's start).  out_lcp[0] = 0.
+ * *ncmp counts character comparisons.  Returns 0, or <0 on bad input. */
+int ssort_oracle_lcp_merge(const uint8_t *chars, uint64_t nchars, const uint64_t *offsets,
+                           const uint32_t *lengths, uint32_t n, uint32_t flags,
+                           const uint32_t *run_begin, uint32_t K, int binary,
+                           const uint32_t *perm_in, const uint32_t *lcp_in,
+                           uint32_t *out_perm, uint32_t *out_lcp, uint64_t *ncmp)
+{
+    if (K < 1 || run_begin[0] != 0 || (binary && K != 2)) return -3;
+    for (uint32_t k = 0; k < K; ++k)
+        if (run_begin[k + 1] < run_begin[k]) return -3;
+    uint64_t total = run_begin[K];
+    for (uint64_t p = 0; p < total; ++p)
+        if (perm_in[p] >= n) return -3;
+    strs_t S;
+    int rc = load_strs(&S, chars, nchars, offsets, lengths, n, flags);
+    if (rc) { free_strs(&S); return rc; }
+    uint64_t cnt = 0;
+    uint32_t *tmp = (uint32_t *)malloc(sizeof(uint32_t) * (total ? total : 1));
+    if (!tmp) { free_strs(&S); return -1; }
+    uint32_t *ol = out_lcp ? out_lcp : tmp;
+    if (binary) {
+        binary_merge(&S, perm_in, lcp_in, run_begin[1], perm_in + run_begin[1], lcp_in + run_begin[1],
+                     run_begin[2] - run_begin[1], out_perm, ol, &cnt);
+        if (total) ol[0] = 0;
+    } else {
+        rc = kway_merge(&S, run_begin, K, perm_in, lcp_in, out_perm, ol, &cnt);
+    }
+    if (ncmp) *ncmp = cnt;
+    free(tmp);
+    free_strs(&S);
+    return rc;
+}
+
+/* LCP-mergesort of the strings a[0..m) into (out, hout) by halving (K = 2,
+ * Algorithm 3) or K-way splitting (Algorithm 4); scratch buffers of m. */
+static int mergesort_rec(const strs_t *S, uint32_t *a, uint32_t *h, uint64_t m, uint32_t K,
+                         uint32_t *tp, uint32_t *th, uint64_t *cnt)
+{
+    if (m <= 1) {
+        if (m) h[0] = 0;
+        return 0;
+    }
+    const uint32_t parts = K;   /* K parts even when m < K (some empty) */
+    uint32_t rb[65];
+    for (uint32_t k = 0; k <= parts; ++k) rb[k] = (uint32_t)(m * k / parts);
+    for (uint32_t k = 0; k < parts; ++k)
+        if (mergesort_rec(S, a + rb[k], h + rb[k], rb[k + 1] - rb[k], K, tp + rb[k], th + rb[k], cnt)) return -1;
+    if (K == 2) {
+        binary_merge(S, a, h, rb[1], a + rb[1], h + rb[1], m - rb[1], tp, th, cnt);
+    } else if (kway_merge(S, rb, parts, a, h, tp, th, cnt)) {
+        return -1;
+    }
+    memcpy(a, tp, sizeof(uint32_t) * m);
+    memcpy(h, th, sizeof(uint32_t) * m);
+    h[0] = 0;
+    return 0;
+}
+
+/* LCP-mergesort (the theorems after Algorithms 3 and 4) of all n strings:
+ * perm and lcp as for ssort_oracle_sort; 2 <= K <= 64.  *ncmp counts
+ * character comparisons.  Returns 0, or <0 on bad input. */
+int ssort_oracle_lcp_mergesort(const uint8_t *chars, uint64_t nchars, const uint64_t *offsets,
+                               const uint32_t *lengths, uint32_t n, uint32_t flags, uint32_t K,
+                               uint32_t *perm, uint32_t *lcp, uint64_t *ncmp)
+{
+    if (K < 2 || K > 64) return -3;
+    strs_t S;
+    int rc = load_strs(&S, chars, nchars, offsets, lengths, n, flags);
+    if (rc) { free_strs(&S); return rc; }
+    uint32_t *tp = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t *th = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!tp || !th) { free(tp); free(th); free_strs(&S); return -1; }
+    for (uint32_t i = 0; i < n; ++i) perm[i] = i;
+    uint64_t cnt = 0;
+    rc = mergesort_rec(&S, perm, lcp, n, K, tp, th, &cnt);
+    if (ncmp) *ncmp = cnt;
+    free(tp);
+    free(th);
+    free_strs(&S);
+    return rc;
 }
