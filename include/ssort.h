@@ -12,7 +12,8 @@
  *  - "device pointer" means memory of the context's GPU (hipMalloc or a torch
  *    CUDA tensor); "host pointer" means ordinary process memory.
  *  - The caller owns every buffer.  No call allocates device memory except
- *    ssort_create / ssort_batch_graph_create / ssort_server_create.
+ *    ssort_create / ssort_graph_create / ssort_server_create (and
+ *    ssort_profile, which creates HIP events).
  *  - Sorting calls are asynchronous: they only enqueue work on `stream` (a
  *    hipStream_t, or NULL for the default stream) and return.  Outputs are valid
  *    once the stream has been synchronised.  They do not synchronise and do not
@@ -53,7 +54,13 @@ typedef enum {
 #define SSORT_TO_END 1u    /* string i runs from offsets[i] to the end of chars (suffixes) */
 
 /* Input string set (a host struct holding device pointers).
- *  chars    device, nchars bytes, any alignment; never read outside [0, nchars).
+ *  chars    device, nchars bytes, any alignment.  Characters are fetched as
+ *           whole aligned 8-byte words: the kernels read only aligned words
+ *           that hold at least one byte of [chars, chars + nchars), so a read
+ *           may touch up to 7 bytes before chars or after chars + nchars
+ *           inside those words (the same pages as the buffer's first and
+ *           last bytes, always mapped when the buffer is); those bytes are
+ *           never used and may hold anything.
  *  offsets  device uint64: n+1 CSR offsets (string i = chars[offsets[i], offsets[i+1]))
  *           when lengths is NULL and SSORT_TO_END is not set; else n start offsets.
  *  lengths  device uint32[n] or NULL.
@@ -76,7 +83,7 @@ typedef struct {
  *                  implementation details of S5.
  *  keys_per_thread keys each thread classifies at a time: 4 or 8.
  *  base_threshold  segments of at most this many strings go to the LCP-aware
- *                  base case (64..1024).
+ *                  base case (16..1024).
  *  flags           SSORT_VALIDATE: check strings for bounds and zero bytes
  *                  first (one extra pass over the characters);
  *                  SSORT_EQUAL: classify with an equality test at every tree
@@ -138,8 +145,9 @@ typedef struct {
      * still occupied, 16 group-descriptor array full, 32 task or descriptor
      * outside the string range, 64 base-case chunk too large, 128
      * redistribution target outside its segment, 256 whole-GPU level tables
-     * full, 512 merge job rank or run index out of range, 1024 an output
-     * permutation entry outside its set at a bucket seam */
+     * full, 512 merge: an index outside the set, a sample rank out of range,
+     * or a cut row unwritten or out of order, 1024 an output permutation
+     * entry outside its set at a bucket seam */
     uint64_t error_bits;
 } ssort_stats_t;
 
@@ -174,8 +182,10 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
                                 uint32_t m, uint32_t *out_perm, uint32_t *out_lcp, void *ws,
                                 size_t ws_bytes, void *stream);
 
-/* Device-side errors of the last sort enqueued with this context; call after
- * synchronising its stream.  Resets the error word. */
+/* Device-side errors of the last sort or merge enqueued with this context;
+ * call after synchronising its stream (the call copies the error word on
+ * `stream` and waits for it).  The word is not reset here: the next sort or
+ * merge clears it when it starts. */
 ssort_status ssort_query_error(ssort_ctx *ctx, void *stream);
 
 /* Counters of the last sort with this context (after synchronising). */
@@ -210,8 +220,13 @@ const char *ssort_strerror(ssort_status s);
  *  run_begin HOST uint32[K+1], run_begin[0] = 0, non-decreasing; run k is
  *            positions run_begin[k] .. run_begin[k+1]-1 of perm_in / lcp_in;
  *            n = run_begin[K] strings in all; 1 <= K <= 32
- *  perm_in   device uint32[n]: indices into `in`; each run sorted, equal
- *            strings in index order (as ssort_sort returns them)
+ *  perm_in   device uint32[n]: indices into `in`, each index in at most one
+ *            run (distinct over all runs); each run sorted by (string, index),
+ *            i.e. equal strings in index order (as ssort_sort returns them).
+ *            Runs that break this are detected on the device (an index outside
+ *            the set, two samples of the same rank, cuts out of order) and
+ *            reported as SSORT_EDEVICE by ssort_query_error; they never make
+ *            the merge access memory outside its buffers.
  *  lcp_in    device uint32[n]: lcp_in[p] = LCP of the strings at positions
  *            p-1 and p of the same run; the entry at a run's start is ignored
  *  out_perm  device uint32[n]: all indices sorted, equal strings by index

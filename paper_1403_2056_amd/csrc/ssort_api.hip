@@ -461,7 +461,7 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
     M.n = n;
     M.g = MERGE_G;
     M.nsamp = L.nsamp;
-    hipLaunchKernelGGL(ssm::k_mreset, dim3(1), dim3(64), 0, s, M);
+    hipLaunchKernelGGL(ssm::k_mreset, dim3(grid_for((uint64_t)(L.nsamp + 1) * K)), dim3(NT), 0, s, M);
     hipLaunchKernelGGL(ssm::k_mcache, dim3(grid_for(n)), dim3(NT), 0, s, M);
     {
         // KP lanes per sample (KP: the smallest power of two >= K, at most 32)

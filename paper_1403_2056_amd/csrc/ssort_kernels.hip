@@ -1137,8 +1137,8 @@ __global__ void k_init(Params P, unsigned long long cap) {
 }
 
 // Alphabet compression, first pass: the byte values that occur in the
-// character buffer (every aligned word that holds a byte of it; bytes outside
-// it are skipped; the value 0 ends strings and is never a character).  Each
+// character buffer (aligned words inside it, the partial words at its two
+// ends byte by byte; the value 0 ends strings and is never a character).  Each
 // thread keeps a 256-bit set in registers, then ORs it into the workgroup's
 // and the device's.
 __global__ __launch_bounds__(NT) void k_alpha_scan(Params P) {
@@ -1151,8 +1151,15 @@ __global__ __launch_bounds__(NT) void k_alpha_scan(Params P) {
     uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)NT + threadIdx.x; i < nw; i += (uint64_t)gridDim.x * NT) {
         const uintptr_t wa = a0 + 8 * i;
-        const uint64_t w = *(const uint64_t *)wa;
         const bool whole = wa >= a && wa + 8 <= e;
+        // the two edge words are read byte by byte: no load leaves the buffer
+        uint64_t w = 0;
+        if (whole) {
+            w = *(const uint64_t *)wa;
+        } else {
+            for (int b = 0; b < 8; ++b)
+                if (wa + b >= a && wa + b < e) w |= (uint64_t)*(const uint8_t *)(wa + b) << (8 * b);
+        }
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const uint32_t c = (uint32_t)(w >> (8 * b)) & 0xFF;

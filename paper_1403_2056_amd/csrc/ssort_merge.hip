@@ -226,18 +226,31 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         atomicOr(M.err, ssd::ERR_MERGE);
         return;
     }
-    // this job: for each run, the elements between cut rows j and j+1
-    uint32_t out = 0;
+    // this job: for each run, the elements between cut rows j and j+1; a
+    // row the sample search left unwritten (two samples of the same rank:
+    // runs that are not sorted by (string, index), or an index in two runs)
+    // or cuts out of order end the merge with a device error, never an access
+    uint32_t out = 0, len = 0;
+    bool bad = false;
     for (uint32_t r = 0; r < KP; ++r) {
         if (r < K) {
             const uint32_t a = M.cuts[(size_t)j * K + r];
             const uint32_t b = (j + 1 < M.nsamp) ? M.cuts[(size_t)(j + 1) * K + r] : M.rb[r + 1] - M.rb[r];
+            bad |= a == SENT || b == SENT || a > b || b > M.rb[r + 1] - M.rb[r];
+            if (bad) break;
             L.pos[r][me] = M.rb[r] + a;
             L.end[r][me] = M.rb[r] + b;
             out += a;
+            len += b - a;
         } else {
             L.pos[r][me] = L.end[r][me] = 0;
         }
+    }
+    // jobs tile the output: job 0 starts at 0 and job j+1 where job j ends,
+    // so every output position is written once
+    if (bad || (j == 0 && out != 0) || out > M.n || len > M.n - out) {
+        atomicOr(M.err, ssd::ERR_MERGE);
+        return;
     }
     // players: the runs' first elements of the job, LCP 0 against the empty
     // string; the tree is built bottom-up with the winners of subtrees kept
@@ -332,7 +345,8 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     }
 }
 
-// LCP between the first output of each job and the string before it.
+// LCP between the first output of each job and the string before it (after
+// k_mmerge has checked every cut row: it runs only without a device error).
 __global__ void k_mseam(MergeParams M) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M.nsamp || *M.err) return;
@@ -343,7 +357,7 @@ __global__ void k_mseam(MergeParams M) {
         qe = 0;
         for (uint32_t r = 0; r < M.K; ++r) qe += M.cuts[(size_t)(j + 1) * M.K + r];
     }
-    if (q >= qe) return;
+    if (q >= qe || qe > M.n) return;
     if (q == 0) {
         M.hout[0] = 0;
         return;
@@ -352,7 +366,12 @@ __global__ void k_mseam(MergeParams M) {
     M.hout[q] = cmp_from(M, M.pout[q - 1], M.pout[q], 0, &less);
 }
 
+// Clear the error word and mark every cut row unwritten (a kernel, not a
+// memset, so that a captured graph holds no memset node).
 __global__ void k_mreset(MergeParams M) {
+    const size_t total = (size_t)(M.nsamp + 1) * M.K;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+        M.cuts[i] = SENT;
     if (threadIdx.x == 0 && blockIdx.x == 0) *M.err = 0;
 }
 

@@ -25,6 +25,9 @@ STATUS = {
 }
 
 
+STATUS_CODES = {name: code for code, name in STATUS.items()}
+
+
 class SsortError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         self.code = code
@@ -192,7 +195,21 @@ class Sorter:
         _check(lib().ssort_create(device, ctypes.byref(self.tuning), ctypes.byref(h)), "ssort_create")
         self._h = h
         self._ws = None
+        self._mws = None
         self._torch = torch
+
+    def _retire(self, t):
+        """Drop a workspace being replaced only after the device has finished
+        with it (a sort or merge enqueued earlier may still use it)."""
+        if t is not None:
+            self._torch.cuda.synchronize(t.device)
+
+    def _used_on(self, t, stream):
+        """A buffer the library uses on a stream other than the current one:
+        tell the caching allocator, so that it does not hand the memory to a
+        new tensor of the current stream while that work runs."""
+        if stream is not None and t is not None and stream != self._torch.cuda.current_stream(t.device):
+            t.record_stream(stream)
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -223,6 +240,7 @@ class Sorter:
     def workspace(self, n: int, m: int = 1):
         need = self.workspace_bytes(n, m)
         if self._ws is None or self._ws.numel() < need:
+            self._retire(self._ws)
             self._ws = self._torch.empty(need, dtype=self._torch.uint8, device=f"cuda:{self.device}")
         return self._ws
 
@@ -237,6 +255,8 @@ class Sorter:
             out_lcp = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         if ws is None:
             ws = self.workspace(n)
+        for t in (ws, out_perm, out_lcp):
+            self._used_on(t, stream)
         st = s.struct()
         _check(lib().ssort_sort(self._h, ctypes.byref(st), _ptr(out_perm), _ptr(out_lcp) if with_lcp else None,
                                 _ptr(ws), ws.numel(), _stream(stream)), "ssort_sort")
@@ -254,6 +274,8 @@ class Sorter:
             out_lcp = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         if ws is None:
             ws = self.workspace(n, m)
+        for t in (ws, out_perm, out_lcp):
+            self._used_on(t, stream)
         st = s.struct()
         _check(lib().ssort_sort_batched(self._h, ctypes.byref(st), _ptr(set_begin), m, _ptr(out_perm),
                                         _ptr(out_lcp) if with_lcp else None, _ptr(ws), ws.numel(),
@@ -273,10 +295,18 @@ class Sorter:
             out_perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         if with_lcp and out_lcp is None:
             out_lcp = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        for t in (out_perm, out_lcp):
+            self._used_on(t, stream)
         if ws is None:
+            # kept on the Sorter until a larger one is needed: the library's
+            # error word and statistics live in it after the call returns
             b = ctypes.c_size_t()
             _check(lib().ssort_merge_workspace_bytes(self._h, rb, K, ctypes.byref(b)), "ssort_merge_workspace_bytes")
-            ws = torch.empty(max(b.value, 1), dtype=torch.uint8, device=dev)
+            if self._mws is None or self._mws.numel() < b.value:
+                self._retire(self._mws)
+                self._mws = torch.empty(max(b.value, 1), dtype=torch.uint8, device=dev)
+            ws = self._mws
+        self._used_on(ws, stream)
         st = s.struct()
         _check(lib().ssort_merge(self._h, ctypes.byref(st), rb, K, _ptr(perm_in), _ptr(lcp_in), _ptr(out_perm),
                                  _ptr(out_lcp) if with_lcp else None, _ptr(ws), ws.numel(), _stream(stream)),

@@ -126,3 +126,44 @@ def test_merge_rejects_bad_runs(sorter):
         sorter.merge(d, [0, 60, 50, 100], t, t)
     with pytest.raises(ssort.SsortError):
         sorter.merge(d, [0] + [100] * 33, t, t)
+
+
+def test_merge_index_in_two_runs_is_a_device_error(sorter):
+    """An index at the start of two runs gives two samples of the same rank,
+    so one cut row stays unwritten: the merge ends with SSORT_EDEVICE (error
+    bit 512) instead of reading the row."""
+    from paper_1403_2056_amd import ssort
+    import os
+    ss = W.plain(4000, seed=75)
+    strs = ss.strings()
+    rp = oracle.sort(ss)[0].astype(np.uint32)
+    x = rp[0]                          # the set's smallest (string, index)
+    runs = [rp[0::2], np.concatenate([[x], rp[1::2]]).astype(np.uint32)]   # x starts both runs
+    lcps = [np.array([0] + [len(os.path.commonprefix([strs[r[i - 1]], strs[r[i]]])) for i in range(1, len(r))],
+                     dtype=np.uint32) for r in runs]
+    rb = [0, len(runs[0]), len(runs[0]) + len(runs[1])]
+    pin, hin = np.concatenate(runs), np.concatenate(lcps)
+    d = ssort.strings_to_device(ss)
+    sorter.merge(d, rb, torch.from_numpy(pin.view(np.int32)).cuda(), torch.from_numpy(hin.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    assert sorter.query_error() == ssort.STATUS_CODES["SSORT_EDEVICE"]
+    assert sorter.stats()["error_bits"] & 512
+    # the context still sorts and merges correctly afterwards
+    merge_parity(sorter, ss, 3, 12, "after a rejected merge")
+
+
+def test_merge_error_word_outlives_the_call(sorter):
+    """The merge workspace (with the error word ssort_query_error reads) stays
+    allocated after the call, so an unrelated allocation filled with ones
+    cannot land on it."""
+    from paper_1403_2056_amd import ssort
+    ss = W.plain(30000, seed=76)
+    rb, pin, hin = runs_from(ss, 4, 13)
+    d = ssort.strings_to_device(ss)
+    sorter.merge(d, rb, torch.from_numpy(pin.view(np.int32)).cuda(), torch.from_numpy(hin.view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    junk = [torch.full((1 << 16,), -1, dtype=torch.int64, device="cuda") for _ in range(64)]
+    torch.cuda.synchronize()
+    assert sorter.query_error() == 0
+    assert sorter.stats()["error_bits"] == 0
+    del junk
