@@ -116,11 +116,39 @@ def device_error_exit(sorter, stream, what):
         raise SystemExit(f"device error during {what}: status {rc}, error mask {bits:#x}")
 
 
-def bench_batched(args):
+BATCHED_FALLBACK_TUNING = {"v": 63, "keys_per_thread": 4, "base_threshold": 256}
+
+
+def host_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (the share of a shared host)."""
+    t = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        t = min(t, int(env))
+    return max(1, t)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def bench_batched(args, embedded: bool = False):
     """Batched form: 4096 independent sets (sizes 2^U(6,18), geometric lengths
     with mean 24, 95 printable bytes) sorted by one graph-captured launch,
     against the same sets sorted one at a time (one ssort_sort per set, each
-    synchronised).  The tuning is the autotuner's choice for this workload."""
+    synchronised).  The tuning is the autotuner's cached choice for this
+    workload (tuned here only with --retune, or when nothing is cached and the
+    batched mode runs on its own).  Returns the result dict; exits non-zero
+    when a checked set differs from the oracle or the graph's output differs
+    from the one-at-a-time output."""
     import torch
     from paper_1403_2056_amd import autotune, ssort, workloads
     t0 = time.time()
@@ -133,7 +161,11 @@ def bench_batched(args):
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     tun = autotune.lookup(arch, "batched", n)
     table = None
+    tuned_from = "cache"
+    if tun is None and embedded and not args.retune:
+        tun, tuned_from = dict(BATCHED_FALLBACK_TUNING), "fallback (nothing cached)"
     if tun is None or args.retune:
+        tuned_from = "tuned now"
         # tune on the first quarter of the sets (same size distribution)
         q = args.sets // 4
         nq = int(sb[q])
@@ -181,13 +213,15 @@ def bench_batched(args):
         plain.sort(v, out_perm=perm1[a:b], out_lcp=lcp1[a:b], ws=ws)
         torch.cuda.synchronize()
     t_one = time.perf_counter() - t2
+    device_error_exit(plain, None, "one-at-a-time sorts")
     same_perm = bool(torch.equal(g.perm[:n], perm1))
     same_lcp = bool(torch.equal(g.lcp[:n], lcp1))
     out = {"metric": "strings/sec batched (one graph launch) vs one-at-a-time", "value": round(n / t_graph, 1),
            "unit": "strings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(t_graph * 1000, 3), "higher_is_better": True, "dtype": "u8", "data": "synthetic",
            "config": {"workload": f"batched: {args.sets} sets of 2^U(6,{args.size_log2_max or 18}) strings, geometric lengths mean 24, "
-                                  "95 printable bytes", "n": n, "N": int(len(ss.chars)), "tuning": tun},
+                                  "95 printable bytes", "n": n, "N": int(len(ss.chars)), "tuning": tun,
+                      "tuning_from": tuned_from},
            "one_at_a_time_ms": round(t_one * 1000, 3), "one_at_a_time_strings_per_s": round(n / t_one, 1),
            "batched_vs_one_at_a_time": round(t_one / t_graph, 2),
            "identical_to_one_at_a_time": same_perm and same_lcp}
@@ -205,7 +239,14 @@ def bench_batched(args):
             sub = workloads.StringSet(ss.chars, ss.offsets[a: b + 1].copy(), None, 0, b - a, {})
             rp, rh = oracle.sort(sub)
             bad += int(not (np.array_equal(p[a:b], rp) and np.array_equal(h[a:b], rh)))
-        out["oracle_checked_sets"] = 32 - bad
+        checked = min(32, args.sets)
+        out["oracle_checked_sets"] = checked - bad
+        out["oracle_mismatching_sets"] = bad
+        if bad:
+            print(json.dumps(out), flush=True)
+            raise SystemExit(f"batched output differs from the oracle in {bad} of {checked} checked sets")
+        if embedded:
+            return out
         t3 = time.perf_counter()
         done = 0
         for k in range(args.sets):
@@ -217,7 +258,13 @@ def bench_batched(args):
         tc = time.perf_counter() - t3
         out["cpu_baseline"] = {"value": round(done / tc, 1), "unit": "strings/s", "cores": 1, "kind": "oracle",
                                "sample": f"the first {done} strings of the batch, set by set"}
+    if not (same_perm and same_lcp):
+        print(json.dumps(out), flush=True)
+        raise SystemExit("the graph-launched batch differs from the one-at-a-time sorts")
+    if embedded:
+        return out
     print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_serve(args):
@@ -286,6 +333,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="plain mode: skip the batched block (4096 sets, graph launch vs one at a time)")
+    ap.add_argument("--batched-steps", type=int, default=5, help="timed graph launches of the batched block")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a device copy of this many GiB (counter scaling runs)")
     ap.add_argument("--v", type=int, default=255)
@@ -392,12 +442,25 @@ def main():
         chk = oracle.check(ss, p, h)
         if chk != -1:
             raise SystemExit(f"GPU output fails the oracle's checker at position {chk}")
+        # the oracle as it stands, on every host thread this process may use
+        # (same multikey quicksort, subproblems above 2^16 strings on a shared
+        # job queue), then on one thread
+        T = host_threads()
         t1 = time.perf_counter()
-        oracle.sort(ss)
+        rp, rh = oracle.sort(ss, threads=T)
         tc = time.perf_counter() - t1
-        cpu = {"value": round(n / tc, 1), "unit": "strings/s", "cores": 1, "kind": "oracle",
-               "sample": f"the same {n}-string input, whole sort with LCP array, single thread",
-               "seconds": round(tc, 3), "checked_gpu_output": True}
+        same = bool(np.array_equal(rp, p) and np.array_equal(rh, h))
+        del rp, rh
+        t1 = time.perf_counter()
+        oracle.sort(ss, threads=1)
+        t1c = time.perf_counter() - t1
+        cpu = {"value": round(n / tc, 1), "unit": "strings/s", "cores": T, "kind": "oracle",
+               "sample": f"the same {n}-string input, whole sort with LCP array, {T} host threads",
+               "seconds": round(tc, 3), "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+               "single_core": {"value": round(n / t1c, 1), "unit": "strings/s", "seconds": round(t1c, 3)},
+               "checked_gpu_output": True, "identical_to_gpu_output": same}
+        if not same:
+            raise SystemExit("the oracle's sort differs from the GPU output")
 
     out = {
         "metric": "strings/sec + distinguishing-prefix GB/s (frac of HBM peak); batched vs plain",
@@ -423,6 +486,14 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if not args.no_batched:
+        # the batched form (the metric's "batched vs plain"): 4096 sets at
+        # full size, one graph launch against one set at a time
+        del d, perm, lcp, ws, sorter
+        torch.cuda.empty_cache()
+        ba = argparse.Namespace(**vars(args))
+        ba.sets, ba.size_log2_max, ba.steps, ba.warmup = 4096, 18, args.batched_steps, 2
+        out["batched"] = bench_batched(ba, embedded=True)
     print(json.dumps(out), flush=True)
 
 
