@@ -12,8 +12,9 @@
  *  - "device pointer" means memory of the context's GPU (hipMalloc or a torch
  *    CUDA tensor); "host pointer" means ordinary process memory.
  *  - The caller owns every buffer.  No call allocates device memory except
- *    ssort_create / ssort_graph_create / ssort_server_create (and
- *    ssort_profile, which creates HIP events).
+ *    ssort_graph_create / ssort_server_create (and ssort_profile, which
+ *    creates HIP events); ssort_create may load the library's code on the
+ *    device, which holds the ssort_sort_noalloc array.
  *  - Sorting calls are asynchronous: they only enqueue work on `stream` (a
  *    hipStream_t, or NULL for the default stream) and return.  Outputs are valid
  *    once the stream has been synchronised.  They do not synchronise and do not
@@ -152,8 +153,9 @@ typedef struct {
 } ssort_stats_t;
 
 /* Create a context on HIP device `device` (the current device if < 0).
- * t may be NULL for the default tuning.  Allocates a small control block on
- * the device.  Returns SSORT_EINVAL for an invalid tuning. */
+ * t may be NULL for the default tuning.  Looks up the device address of the
+ * ssort_sort_noalloc array (once per device).  Returns SSORT_EINVAL for an
+ * invalid tuning. */
 ssort_status ssort_create(int device, const ssort_tuning *t, ssort_ctx **out);
 void ssort_destroy(ssort_ctx *ctx);
 ssort_status ssort_get_tuning(const ssort_ctx *ctx, ssort_tuning *t);
@@ -169,6 +171,29 @@ ssort_status ssort_workspace_bytes(const ssort_ctx *ctx, uint32_t n, uint32_t m,
  * n = 0 enqueues nothing. */
 ssort_status ssort_sort(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_perm,
                         uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- sorting without allocation ----
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ssort_sort
+ * without a workspace argument.  The workspace is a device array inside the
+ * library of SSORT_NOALLOC_SCRATCH_BYTES bytes, one per GPU, created when the
+ * library is loaded on that GPU and held until the process ends; the call
+ * itself allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  The caller still passes the inputs and outputs, as for
+ * ssort_sort.  Returns SSORT_EWORKSPACE, enqueuing nothing, when
+ * ssort_workspace_bytes(ctx, n, 1) exceeds the array (about 1.2 million
+ * strings with the default tuning; 2^20 strings fit with every
+ * base_threshold of at least 32), and SSORT_EDEVICE if the array's device
+ * address could not be looked up when the context was created.
+ * Every call on one GPU uses that GPU's one array, whatever the context:
+ * calls whose work overlaps on the device (different streams, or different
+ * host threads) race and give undefined results; serialise them (one
+ * stream, or a synchronisation between calls).  The array keeps the last
+ * call's contents; each call clears what it needs cleared.
+ * ssort_query_error and ssort_stats report on it as on a workspace. */
+#define SSORT_NOALLOC_SCRATCH_BYTES (64u << 20)
+ssort_status ssort_sort_noalloc(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_perm,
+                                uint32_t *out_lcp, void *stream);
 
 /* Sort m independent sets in one launch sequence.  The strings of all sets
  * form one string space `flat`; set s is strings [set_begin[s], set_begin[s+1]).

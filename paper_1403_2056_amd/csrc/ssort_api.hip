@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <algorithm>
+#include <mutex>
 
 #include "ssort.h"
 #include "ssort_kernels.hip"
@@ -21,12 +22,39 @@ struct ssort_ctx {
     unsigned long long wall_khz;
     uint32_t wait_ms;
     void *last_ws;
+    void *scratch;     // this device's copy of `scratch` (ssort_sort_noalloc), or null
     int prof;
     hipEvent_t ev[4];
 };
 
+// Workspace of ssort_sort_noalloc, for callers that cannot allocate: a
+// file-scope device array, one copy per GPU the library is loaded on, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host the name is a stand-in, not a device address): each
+// context looks up its device's address once, in ssort_create, and passes
+// that.
+static __device__ __align__(256) unsigned char scratch[SSORT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];   // device address of `scratch` per device, once looked up
+
+// The device address of this device's `scratch` (the device is current).
+void *scratch_of(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_ptr[device] = p;
+    }
+    return scratch_ptr[device];
+}
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -273,6 +301,7 @@ ssort_status ssort_create(int device, const ssort_tuning *t, ssort_ctx **out) {
     int nb = 0;
     if (occupancy(tun, &nb) != hipSuccess || nb < 1) nb = 1;
     c->worker_blocks = c->cus * nb;
+    c->scratch = scratch_of(device);
     *out = c;
     return SSORT_OK;
 }
@@ -359,6 +388,21 @@ ssort_status ssort_sort(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_p
     if (ctx->prof) (void)hipEventRecord(ctx->ev[3], s);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
+}
+
+ssort_status ssort_sort_noalloc(ssort_ctx *ctx, const ssort_strings *in, uint32_t *out_perm, uint32_t *out_lcp,
+                                void *stream) {
+    if (!ctx) return SSORT_EINVAL;
+    ssort_status st = check_strings(in);
+    if (st != SSORT_OK) return st;
+    if (in->n == 0) return SSORT_OK;
+    if (!out_perm) return SSORT_EINVAL;
+    if (layout(ctx, in->n, 1).total > (size_t)SSORT_NOALLOC_SCRATCH_BYTES) return SSORT_EWORKSPACE;
+    if (!ctx->scratch) return SSORT_EDEVICE;
+    // the same launches as ssort_sort, on the device's scratch array (k_init
+    // clears its control block and queue; every other part is written before
+    // it is read)
+    return ssort_sort(ctx, in, out_perm, out_lcp, ctx->scratch, (size_t)SSORT_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const uint32_t *set_begin, uint32_t m,

@@ -99,6 +99,8 @@ _SIGS = {
     "ssort_merge": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "ssort_sort_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "ssort_sort_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_void_p,
                                           ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_size_t, ctypes.c_void_p]),
@@ -261,6 +263,17 @@ class Sorter:
         _check(lib().ssort_sort(self._h, ctypes.byref(st), _ptr(out_perm), _ptr(out_lcp) if with_lcp else None,
                                 _ptr(ws), ws.numel(), _stream(stream)), "ssort_sort")
         return out_perm[:n], (out_lcp[:n] if with_lcp else None)
+
+    def sort_noalloc(self, s: DeviceStrings, out_perm, out_lcp=None, stream=None):
+        """Enqueue a sort that uses the library's own per-GPU scratch array as
+        its workspace (ssort_sort_noalloc: the call allocates nothing; the
+        caller passes the output tensors)."""
+        for t in (out_perm, out_lcp):
+            self._used_on(t, stream)
+        st = s.struct()
+        _check(lib().ssort_sort_noalloc(self._h, ctypes.byref(st), _ptr(out_perm), _ptr(out_lcp), _stream(stream)),
+               "ssort_sort_noalloc")
+        return out_perm[: s.n], (out_lcp[: s.n] if out_lcp is not None else None)
 
     def sort_batched(self, s: DeviceStrings, set_begin, with_lcp: bool = True, out_perm=None, out_lcp=None,
                      ws=None, stream=None):
