@@ -81,7 +81,13 @@ typedef struct {
  *  v               splitters per classification step, 2^d - 1 with d in 1..8
  *                  (63, 127 or 255 in practice; the tree and its 2v+1 bucket
  *                  counters live in LDS).  Algorithm 1; tree size choice in the
- *                  implementation details of S5.
+ *                  implementation details of S5.  Also 1023, 2047 or 4095:
+ *                  then the first whole-GPU level classifies against that
+ *                  many splitters, with a jump table over the keys' top 12
+ *                  bits for the top of the descent and a distribution in two
+ *                  stable passes by the digits of the bucket number (the
+ *                  multipass distribution and jump tables of the paper's
+ *                  refinements), and every later step uses 255.
  *  keys_per_thread keys each thread classifies at a time: 4 or 8.
  *  base_threshold  segments of at most this many strings go to the LCP-aware
  *                  base case (16..1024).
@@ -269,18 +275,26 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
 /* ---- one classification step with its intermediates (parity checks) ----
  * Runs one step of Algorithm 1 over all n strings of `in` at common depth
  * `depth` (the caller guarantees the strings share that prefix), on the input
- * order, with the library's own sample and splitters.  Outputs (device):
- *  keys      uint64[n]   8-byte big-endian keys at `depth` (zero past the end)
- *  split     uint64[256] sorted splitters x_0..x_{v'-1} actually used
- *  tree      uint64[256] level-order tree, tree[j-1] = node j
- *  info      uint32[4]   {v', d', number of distinct sample keys, 0}
- *  bucket    uint16[n]   bucket of each string, 0..2v'
- *  hist      uint32[512] strings per bucket
- *  perm      uint32[n]   input indices after the stable redistribution
- * ws as for ssort_sort with n strings. */
+ * order, with the library's own sample and splitters: the whole-GPU level-0
+ * step, wide (v > 255: jump table and two distribution passes) when the
+ * context's tuning asks for it.  Outputs (device):
+ *  keys      uint64[n]    8-byte big-endian keys at `depth` (zero past the end)
+ *  split     uint64[4096] sorted splitters x_0..x_{v'-1} actually used
+ *  tree      uint64[4096] level-order tree, tree[j-1] = node j
+ *  jump      uint16[4096] or NULL: the wide step's jump table (jump[p] = the
+ *                         node where the descent of keys with top 12 bits p
+ *                         continues, > v' for a leaf); untouched when narrow
+ *  info      uint32[4]    {v', d', number of distinct sample keys, jump-table
+ *                         bits (0 for a narrow step)}
+ *  bucket    uint16[n]    bucket of each string (input order), 0..2v'
+ *  hist      uint32[8192] strings per bucket
+ *  perm      uint32[n]    input indices after the stable redistribution
+ * Entries past v' (2v'+1 for hist) are zero up to 256 (512) for a narrow
+ * step and up to 4096 (8192) for a wide one.  ws as for ssort_sort with n
+ * strings. */
 ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t depth,
-                              uint64_t *keys, uint64_t *split, uint64_t *tree, uint32_t *info,
-                              uint16_t *bucket, uint32_t *hist, uint32_t *perm, void *ws,
+                              uint64_t *keys, uint64_t *split, uint64_t *tree, uint16_t *jump,
+                              uint32_t *info, uint16_t *bucket, uint32_t *hist, uint32_t *perm, void *ws,
                               size_t ws_bytes, void *stream);
 
 /* ---- graph-captured launch (the batched form) ----

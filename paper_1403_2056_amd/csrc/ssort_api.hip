@@ -9,6 +9,7 @@
 
 #include "ssort.h"
 #include "ssort_kernels.hip"
+#include "ssort_wide.hip"
 #include "ssort_merge.hip"
 #include "ssort_serve.hip"
 
@@ -73,9 +74,23 @@ uint32_t grid_for(uint64_t work) {
 
 struct Layout {
     size_t ctl, r0, r1, bkt, ring, lseg[LMAX], t2s[LMAX], lsplit[LMAX], ltot[LMAX], hist, desc, alpha, total;
+    size_t wsplit, wst, wen, btmp;   // wide level 0 only (0 otherwise)
     uint64_t cap;
     uint32_t maxseg, maxtiles, tile;
 };
+
+// Splitters of the wide level 0 (0: every level narrow); the worker's steps
+// use at most VMAX.
+uint32_t wide_v(const ssort_tuning &t) { return t.v > (uint32_t)VMAX ? t.v : 0u; }
+uint32_t narrow_v(const ssort_tuning &t) { return t.v > (uint32_t)VMAX ? (uint32_t)VMAX : t.v; }
+
+// Bits of the wide level's second distribution digit: bucket numbers are
+// below 2(v+1) = 2^(WLO + hbits).
+uint32_t wide_hbits(uint32_t wv) {
+    uint32_t b = 0;
+    while ((1u << b) < 2 * (wv + 1)) ++b;
+    return b - WLO;
+}
 
 Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     Layout L;
@@ -91,8 +106,10 @@ Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     // in a worker step; at most one per bucket when formed by a level); twice
     // that bound leaves every slot's previous occupant consumed long before
     // the slot is reused
+    const uint32_t wv = wide_v(c->tun);
+    const uint64_t nb0 = wv ? 2 * (uint64_t)wv + 1 : (uint64_t)NBMAX;   // buckets of a level-0 segment
     const uint64_t live = 2 * (uint64_t)n / (c->tun.base_threshold + 1) + (uint64_t)n / 128 + m +
-                          (uint64_t)NBMAX * (2 * L.maxseg + 1) + (uint64_t)c->worker_blocks;
+                          (nb0 + NBMAX) * (L.maxseg + 1) + (uint64_t)c->worker_blocks;
     L.cap = next_pow2(2 * live + 1024);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -114,13 +131,21 @@ Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     L.hist = take(4 * (size_t)NBPAD * L.maxtiles);
     L.desc = take(sizeof(GroupDesc) * (size_t)n);   // at most one descriptor per base-case group
     L.alpha = take(sizeof(Alphabet));
+    L.wsplit = L.wst = L.wen = L.btmp = 0;
+    if (wv) {
+        L.wsplit = take(sizeof(WSplit) * (size_t)L.maxseg);
+        L.wst = take(4 * (size_t)WNBPAD * L.maxseg);
+        L.wen = take(4 * (size_t)WNBPAD * L.maxseg);
+        L.btmp = take(2 * (size_t)n);
+    }
     L.total = off;
     return L;
 }
 
 bool valid_tuning(const ssort_tuning &t) {
     const uint32_t v = t.v;
-    if (v < 1 || v > VMAX || ((v + 1) & v) != 0) return false;
+    if (v < 1 || ((v + 1) & v) != 0) return false;
+    if (v > VMAX && v != 1023 && v != 2047 && v != (uint32_t)WVMAX) return false;
     if (t.keys_per_thread != 4 && t.keys_per_thread != 8) return false;
     if (t.base_threshold < 16 || t.base_threshold > (uint32_t)CH) return false;
     if (t.flags & ~(SSORT_VALIDATE | SSORT_EQUAL | SSORT_ALPHABET)) return false;
@@ -189,17 +214,47 @@ void launch_seam(const ssort_ctx *c, const Params &P, hipStream_t s) {
 // The whole-GPU levels (grids sized for each level's capacity; workgroups
 // beyond the level's actual count exit at once).  With schedule = false only
 // level 0 runs, without turning its buckets into tasks (the debug step).
+// Wide level 0 (v > 255): sample and tree with its jump table, classify,
+// two stable distribution passes by the digits of the bucket number, bucket
+// bounds, children.
+void launch_wide_level(const ssort_ctx *c, const Params &P, const Layout &L, bool schedule, hipStream_t s) {
+    const int K = c->tun.keys_per_thread;
+    const bool z = packed(c) && P.alpha;
+    const uint32_t hb = wide_hbits(P.wv);
+    const size_t lds = 8 * ((size_t)P.wv + 1) + 2 * ((size_t)1 << JA) + 4 * ((size_t)1 << WLO);
+    const dim3 tiles(L.maxtiles), b(NT);
+    if (z) hipLaunchKernelGGL((k_wsample<true>), dim3(L.maxseg), b, 0, s, P);
+    else hipLaunchKernelGGL((k_wsample<false>), dim3(L.maxseg), b, 0, s, P);
+    if (K == 4 && z) hipLaunchKernelGGL((k_wclassify<4, true>), tiles, b, lds, s, P);
+    else if (K == 4) hipLaunchKernelGGL((k_wclassify<4, false>), tiles, b, lds, s, P);
+    else if (z) hipLaunchKernelGGL((k_wclassify<8, true>), tiles, b, lds, s, P);
+    else hipLaunchKernelGGL((k_wclassify<8, false>), tiles, b, lds, s, P);
+    hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), b, 0, s, P, 0u, 1u << WLO);
+    if (K == 4) hipLaunchKernelGGL((k_wscatter<4, 1>), tiles, b, 0, s, P, hb);
+    else hipLaunchKernelGGL((k_wscatter<8, 1>), tiles, b, 0, s, P, hb);
+    hipLaunchKernelGGL(k_whist2, tiles, b, 0, s, P, hb);
+    hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), b, 0, s, P, 0u, 1u << hb);
+    if (K == 4) hipLaunchKernelGGL((k_wscatter<4, 2>), tiles, b, 0, s, P, hb);
+    else hipLaunchKernelGGL((k_wscatter<8, 2>), tiles, b, 0, s, P, hb);
+    hipLaunchKernelGGL(k_wbounds, tiles, b, 0, s, P);
+    if (schedule) hipLaunchKernelGGL(k_wschedule, dim3(L.maxseg), b, 0, s, P);
+}
+
 void launch_levels(const ssort_ctx *c, const Params &P, const Layout &L, bool schedule, hipStream_t s) {
     const int K = c->tun.keys_per_thread;
     const bool z = packed(c) && P.alpha;
     for (uint32_t l = 0; l < (schedule ? (uint32_t)LMAX : 1u); ++l) {
+        if (l == 0 && P.wv) {
+            launch_wide_level(c, P, L, schedule, s);
+            continue;
+        }
         if (z) hipLaunchKernelGGL((k_lvl_sample<true>), dim3(L.maxseg), dim3(NT), 0, s, P, l);
         else hipLaunchKernelGGL((k_lvl_sample<false>), dim3(L.maxseg), dim3(NT), 0, s, P, l);
         if (K == 4 && z) hipLaunchKernelGGL((k_lvl_classify<4, true>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         else if (K == 4) hipLaunchKernelGGL((k_lvl_classify<4, false>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         else if (z) hipLaunchKernelGGL((k_lvl_classify<8, true>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         else hipLaunchKernelGGL((k_lvl_classify<8, false>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
-        hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), dim3(NT), 0, s, P, l);
+        hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), dim3(NT), 0, s, P, l, 0u);
         if (K == 4) hipLaunchKernelGGL((k_lvl_scatter<4>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         else hipLaunchKernelGGL((k_lvl_scatter<8>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         if (schedule) hipLaunchKernelGGL(k_lvl_schedule, dim3(L.maxseg), dim3(NT), 0, s, P, l);
@@ -251,7 +306,14 @@ Params make_params(const ssort_ctx *c, const ssort_strings *in, uint32_t *perm, 
     P.tile = L.tile;
     P.chunk = (uint32_t)chunk_for(c->tun.base_threshold);
     P.tbase = c->tun.base_threshold;
-    P.vmax = c->tun.v;
+    P.vmax = narrow_v(c->tun);
+    P.wv = wide_v(c->tun);
+    if (P.wv) {
+        P.wsplit = (WSplit *)(w + L.wsplit);
+        P.wst = (uint32_t *)(w + L.wst);
+        P.wen = (uint32_t *)(w + L.wen);
+        P.btmp = (uint16_t *)(w + L.btmp);
+    }
     P.equal = (c->tun.flags & SSORT_EQUAL) ? 1u : 0u;
     P.limit_ticks = (unsigned long long)c->wait_ms * c->wall_khz;
     P.limit_iters = (unsigned long long)c->wait_ms * 2000ull;   // polls take well over 0.5 us each
@@ -566,8 +628,8 @@ ssort_status ssort_stats(ssort_ctx *ctx, ssort_stats_t *out, void *stream) {
 }
 
 ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t depth, uint64_t *keys, uint64_t *split,
-                              uint64_t *tree, uint32_t *info, uint16_t *bucket, uint32_t *hist, uint32_t *perm,
-                              void *ws, size_t ws_bytes, void *stream) {
+                              uint64_t *tree, uint16_t *jump, uint32_t *info, uint16_t *bucket, uint32_t *hist,
+                              uint32_t *perm, void *ws, size_t ws_bytes, void *stream) {
     if (!ctx) return SSORT_EINVAL;
     ssort_status st = check_strings(in);
     if (st != SSORT_OK) return st;
@@ -581,8 +643,12 @@ ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t 
     hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, (unsigned long long)L.cap);
     hipLaunchKernelGGL(k_seed, dim3(1), dim3(NT), 0, s, P, 1u, depth, 1u);
     launch_levels(ctx, P, L, false, s);
-    hipLaunchKernelGGL(k_debug_dump, dim3(grid_for(in->n)), dim3(NT), 0, s, P, depth, keys, split, tree, info, bucket,
-                       hist, perm);
+    if (P.wv)
+        hipLaunchKernelGGL(k_wdebug_dump, dim3(grid_for(in->n)), dim3(NT), 0, s, P, depth, keys, split, tree, jump, info,
+                           bucket, hist, perm);
+    else
+        hipLaunchKernelGGL(k_debug_dump, dim3(grid_for(in->n)), dim3(NT), 0, s, P, depth, keys, split, tree, info,
+                           bucket, hist, perm);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
 }

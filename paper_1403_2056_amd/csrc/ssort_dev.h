@@ -278,7 +278,8 @@ __device__ __forceinline__ uint32_t node_of_rank(uint32_t r, uint32_t d) {
     return (1u << (d - 1 - k)) + ((r + 1) >> (k + 1));
 }
 
-__device__ __forceinline__ uint64_t splitter(const Split &sp, uint32_t r) { return sp.tree[node_of_rank(r, sp.d)]; }
+template <typename SP>
+__device__ __forceinline__ uint64_t splitter(const SP &sp, uint32_t r) { return sp.tree[node_of_rank(r, sp.d)]; }
 
 // Bucket of key c: descend the level-order tree going right when c > t_i,
 // then l = i - (v+1) counts the splitters below c; bucket 2l, plus one when
@@ -321,21 +322,23 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 }
 
 // Sample keys and splitters for a segment of `size` strings at depth h, read
-// through `load(e)` (0 <= e < size).  Sample of up to 2(v+1)-1 keys (all
-// strings when the segment is that small, else one pseudo-random pick per
-// stratum), sorted in LDS by rank counting; the distinct sample keys become
+// through `load(e)` (0 <= e < size).  Sample of up to ovs(v+1)-1 keys
+// (oversampling factor ovs; all strings when the segment is that small, else
+// one pseudo-random pick per stratum), sorted in LDS; the distinct sample keys become
 // the splitters when they fit into the tree (the smallest tree 2^d'-1 >= their
 // number, padded by the largest), else v equidistant distinct keys, so that no
 // splitter repeats (cf. the skip-duplicates selection).  Then the level-order
 // tree, the splitter LCPs (xor + count leading zeros) and the end-of-string
-// flags.  `samp`, `srt` need SAMPLE_MAX+1 entries (a power of two: the sort
-// pads to one), `fl` SAMPLE_MAX+1, tmp NW.
-template <typename Load, typename KC>
-__device__ __forceinline__ void select_splitters(Split &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
+// flags.  `samp`, `srt` need ovs(vmax+1) entries (a power of two: the sort
+// pads to one), `fl` as many, tmp NW.  SP is Split, or the wide level's
+// WSplit (same fields, larger arrays).
+template <typename SP, typename Load, typename KC>
+__device__ __forceinline__ void select_splitters(SP &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
                                                  uint32_t equal, uint64_t *samp, uint64_t *srt, uint32_t *fl,
-                                                 uint32_t *tmp, Load load, const KC &kc) {
+                                                 uint32_t *tmp, Load load, const KC &kc, uint32_t ovs = 2) {
     const int tid = tid_here();
-    const uint32_t a = size < (uint32_t)(2 * (vmax + 1) - 1) ? size : (uint32_t)(2 * (vmax + 1) - 1);
+    const uint32_t amax = ovs * (vmax + 1) - 1;
+    const uint32_t a = size < amax ? size : amax;
     const bool all = size <= a;
     const uint32_t stride = all ? 1u : size / a;
     for (uint32_t t = tid; t < a; t += NT) {

@@ -82,6 +82,25 @@ struct __align__(16) GroupDesc {
     uint32_t start, size, depth, pad;
 };
 
+// Wide whole-GPU level (the larger trees of the paper's implementation
+// details, v up to 4095, with the multipass distribution and jump table of its
+// refinements): the splitters of one segment, built by one workgroup and read
+// by every tile.  Same fields as Split, larger arrays, plus the jump table:
+// jump[p] is the tree node where the descent of every key whose top JA bits
+// are p still has to continue (or the leaf it reaches).
+constexpr int WVMAX = 4095;               // largest wide splitter count (d = 12)
+constexpr int WDMAX = 12;
+constexpr int WNBPAD = 8192;              // 2 * WVMAX + 1 buckets, padded
+constexpr int JA = 12;                    // key bits indexing the jump table
+constexpr int WLO = 7;                    // bits of the first distribution digit
+struct WSplit {
+    uint64_t tree[WVMAX + 1];   // level order, tree[1..v]
+    uint16_t jump[1 << JA];
+    uint8_t hl[WVMAX + 1];
+    uint8_t zr[WVMAX + 1];
+    uint32_t v, d, nb, nbits, ndistinct, ulast, equal, q;
+};
+
 // One queue slot (bounded MPMC ring with per-slot sequence numbers).
 struct __align__(32) Slot {
     unsigned long long seq;
@@ -116,6 +135,13 @@ struct Params {
     unsigned long long limit_ticks;
     unsigned long long limit_iters;
     Alphabet *alpha;         // alphabet compression: codes of the input's byte values, else null
+    // wide level 0 (wv > 0 splitters): splitters, bucket bounds per segment
+    // (segment-relative first and one-past-last position of each bucket),
+    // and the bucket numbers between the two distribution passes
+    uint32_t wv;
+    WSplit *wsplit;
+    uint32_t *wst, *wen;
+    uint16_t *btmp;
 };
 
 }  // namespace ssd

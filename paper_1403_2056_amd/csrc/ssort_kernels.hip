@@ -113,24 +113,25 @@ __device__ __forceinline__ void release_wg() {
 // matching by ballots, waves are ordered through per-wave counters, and the
 // records are regrouped by bucket in LDS so that each bucket's run is written
 // contiguously.  run[b] is the output position of the chunk's first element
-// of bucket b and is advanced past the chunk.
-template <int K>
+// of bucket b and is advanced past the chunk.  With PAY, a 16-bit payload per
+// element (the full bucket number, when the buckets here are digits of it)
+// moves with its record into pout.
+template <int K, bool PAY = false>
 struct ScatterLDS {
     uint16_t wcnt[NW][NBPAD];   // per wave and bucket, at most 64*K per chunk
     uint16_t tot[NBPAD];        // per bucket in the chunk, at most NT*K
     uint32_t cs[NBPAD];
     Rec rec[NT * K];
     uint16_t b[NT * K];
+    uint16_t pay[PAY ? NT * K : 1];
     uint32_t run[NBPAD];        // next output position per bucket (a step's own)
 };
 
-template <int K>
-__device__ __forceinline__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, const Split &sp, const uint32_t (&m)[K],
-                              const Rec (&r)[K], uint32_t cnt, uint32_t *run, Rec *out, uint32_t nlim,
-                              unsigned long long *err) {
+template <int K, bool PAY = false>
+__device__ __forceinline__ void scatter_chunk(ScatterLDS<K, PAY> &L, uint32_t *tmp, uint32_t nb, int nbits,
+                              const uint32_t (&m)[K], const Rec (&r)[K], const uint16_t *pay, uint32_t cnt,
+                              uint32_t *run, Rec *out, uint16_t *pout, uint32_t nlim, unsigned long long *err) {
     const int tid = tid_here(), w = tid >> 6, lane = tid & 63;
-    const uint32_t nb = uni(sp.nb);
-    const int nbits = (int)uni(sp.nbits);
     uint32_t *wc = (uint32_t *)&L.wcnt[0][0];
     for (int i = tid; i < NW * NBPAD / 2; i += NT) wc[i] = 0;
     __syncthreads();
@@ -169,14 +170,19 @@ __device__ __forceinline__ void scatter_chunk(ScatterLDS<K> &L, uint32_t *tmp, c
             const uint32_t slot = L.cs[mj] + L.wcnt[w][mj] + rk[j];
             L.rec[slot] = r[j];
             L.b[slot] = (uint16_t)mj;
+            if constexpr (PAY) L.pay[slot] = pay[j];
         }
     }
     __syncthreads();
     for (uint32_t s = tid; s < cnt; s += NT) {
         const uint32_t mb = L.b[s];
         const uint32_t gp = run[mb] + (s - L.cs[mb]);
-        if (gp < nlim) out[gp] = L.rec[s];
-        else atomicOr(err, ERR_SCATTER);
+        if (gp < nlim) {
+            out[gp] = L.rec[s];
+            if constexpr (PAY) pout[gp] = L.pay[s];
+        } else {
+            atomicOr(err, ERR_SCATTER);
+        }
     }
     __syncthreads();
     for (uint32_t b = tid; b < nb; b += NT) run[b] += L.tot[b];
@@ -550,7 +556,8 @@ __device__ __forceinline__ void mark(LDS &L, int i) {
 // output): h for the outer buckets b_0 and b_2v, h plus the splitter LCP for
 // the other range buckets, h + q (8 characters, or more with alphabet
 // compression) for equality buckets.
-__device__ __forceinline__ uint32_t child_depth(const Split &sp, uint32_t h, uint32_t b) {
+template <typename SP>
+__device__ __forceinline__ uint32_t child_depth(const SP &sp, uint32_t h, uint32_t b) {
     if (b & 1) return h + sp.q;
     if (b == 0 || b == sp.nb - 1) return h;
     return h + sp.hl[b >> 1];
@@ -783,7 +790,8 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
                 m[j] = nb;
             }
         }
-        scatter_chunk<K>(L.u.sc, L.tmp, L.sp, m, r, min(CK, S - c0), L.u.sc.run, out, P.S.n, &P.ctl->error);
+        scatter_chunk<K>(L.u.sc, L.tmp, nb, nbits, m, r, nullptr, min(CK, S - c0), L.u.sc.run, out, nullptr, P.S.n,
+                         &P.ctl->error);
     }
     // the redistributed records are visible to this workgroup now; to the
     // others with the one release before the tasks are committed
@@ -1407,12 +1415,14 @@ __global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
 constexpr int CS_B = 16;
 constexpr int CS_R = NT / CS_B;
 constexpr int CS_G = NBPAD / CS_B;   // bucket groups per segment
-__global__ __launch_bounds__(NT) void k_lvl_colscan(Params P, uint32_t l) {
+// nbw > 0: every segment has nbw columns (the digits of a wide level's
+// distribution passes), else its splitters' bucket count.
+__global__ __launch_bounds__(NT) void k_lvl_colscan(Params P, uint32_t l, uint32_t nbw) {
     __shared__ uint32_t part[CS_R][CS_B];
     const uint32_t seg = blockIdx.x / CS_G, grp = blockIdx.x % CS_G;
     if (P.ctl->error || seg >= lvl_count(P, l, 0)) return;
     const LvlSeg g = P.lseg[l][seg];
-    const uint32_t nb = uni(P.lsplit[l][seg].nb);
+    const uint32_t nb = nbw ? nbw : uni(P.lsplit[l][seg].nb);
     if (grp * CS_B >= nb) return;
     const uint32_t b = grp * CS_B + (threadIdx.x % CS_B);
     const uint32_t r = threadIdx.x / CS_B;
@@ -1496,54 +1506,49 @@ __global__ __launch_bounds__(NT) void k_lvl_scatter(Params P, uint32_t l) {
                 m[j] = nb;
             }
         }
-        scatter_chunk<K>(L.sc, L.tmp, L.sp, m, r, min((uint32_t)(NT * K), g.size - c0), L.run, out, P.S.n,
-                         &P.ctl->error);
+        scatter_chunk<K>(L.sc, L.tmp, nb, (int)uni(L.sp.nbits), m, r, nullptr, min((uint32_t)(NT * K), g.size - c0),
+                         L.run, out, nullptr, P.S.n, &P.ctl->error);
     }
 }
 
-struct LvlSchedLDS {
-    Split sp;
-    uint32_t bst[NBPAD];      // bucket starts (segment-relative)
-    uint32_t cnt[NBPAD];
-    uint32_t kind[NBPAD];     // 1 worker task, 2 small (base case)
-    uint32_t rk[NBPAD];       // worker task rank, later small-list position
-    uint32_t psz[NBPAD + 1];  // size prefix over the small list
-    uint16_t lsmall[NBPAD];
-    uint16_t cfirst[NBPAD + 1];
+template <int NBC>
+struct SchedLDS {
+    uint32_t bst[NBC];        // bucket starts (segment-relative)
+    uint32_t cnt[NBC];
+    uint8_t kind[NBC];        // 0 empty or next-level segment, 1 worker task, 2 small (base case), 3 identical
+    uint32_t rk[NBC + 1];     // worker task rank; later the small list's size prefix
+    uint16_t lsmall[NBC];
+    uint16_t cfirst[NBC + 1];
     uint32_t nchunk;
     unsigned long long pos, db;
     uint32_t tmp[NW];
 };
 
-// Children of a level's segment: the next level's segments, worker tasks for
-// the other large buckets, identical strings finished here, and the small
-// buckets as base-case chunk tasks (group descriptors, chunks of at most
-// C - threshold strings, never splitting a group).
-__global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
-    __shared__ LvlSchedLDS L;
-    if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 0)) return;
+// Children of a level's segment, once its bucket sizes and starts are in
+// L.cnt / L.bst: the next level's segments, worker tasks for the other large
+// buckets, identical strings finished here, and the small buckets as
+// base-case chunk tasks (group descriptors, chunks of at most C - threshold
+// strings, never splitting a group).  SP (Split or WSplit, in LDS or device
+// memory) gives the end-of-string flags and splitter LCPs.
+template <int NBC, typename SP>
+__device__ void schedule_buckets(const Params &P, uint32_t l, const LvlSeg &g, uint32_t nb, const SP &sp,
+                                 SchedLDS<NBC> &L) {
     const int tid = threadIdx.x;
-    const LvlSeg g = P.lseg[l][blockIdx.x];
-    load_split(L.sp, &P.lsplit[l][blockIdx.x]);
-    const uint32_t nb = uni(L.sp.nb), h = g.depth;
+    const uint32_t h = g.depth;
     const uint32_t cpar = out_is_r1(g.meta) ? M_PARITY : 0u;
     const Rec *out = out_is_r1(g.meta) ? P.R1 : P.R0;
-    const uint32_t *tot = &P.ltot[l][(size_t)blockIdx.x * NBPAD];
-    for (uint32_t b = tid; b < NBPAD; b += NT) {
-        const uint32_t c = b < nb ? tot[b] : 0u;
-        L.cnt[b] = c;
-        L.bst[b] = c;
+    for (uint32_t b = tid; b < nb; b += NT) {
+        const uint32_t c = L.cnt[b];
         uint32_t kind = 0;
         if (c) {
-            const bool ident = (b & 1) && L.sp.zr[b >> 1];
+            const bool ident = (b & 1) && sp.zr[b >> 1];
             if (ident) kind = 3;
             else if (!(c > LVL_MIN && l + 1 < LMAX)) kind = c > P.tbase ? 1u : 2u;
         }
-        L.kind[b] = kind;
+        L.kind[b] = (uint8_t)kind;
         L.rk[b] = kind == 1 ? 1u : 0u;
     }
     __syncthreads();
-    block_scan(L.bst, (int)nb, L.tmp, true, AddOp(), 0u);
     const uint32_t ntask = uni(block_scan(L.rk, (int)nb, L.tmp, true, AddOp(), 0u));
     // seams and next-level segments
     for (uint32_t b = tid; b < nb; b += NT) {
@@ -1551,7 +1556,7 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
         if (!c) continue;
         if (P.lcp && st > 0) P.lcp[g.begin + st] = SEAM | h;
         if (L.kind[b] == 0)
-            lvl_append(P, l + 1, LvlSeg{g.begin + st, c, child_depth(L.sp, h, b), cpar, 0, 0, g.setbase, 0});
+            lvl_append(P, l + 1, LvlSeg{g.begin + st, c, child_depth(sp, h, b), cpar, 0, 0, g.setbase, 0});
     }
     // identical strings (an equality bucket whose splitter ends the string):
     // already in input order, lcp = length
@@ -1564,25 +1569,39 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
             if (P.lcp && i > 0) P.lcp[st + i] = r.ln;
         }
     }
+    // worker tasks
+    if (tid == 0 && ntask) {
+        add_agent(&P.ctl->pending, (unsigned long long)ntask);
+        L.pos = add_agent(&P.ctl->tail, (unsigned long long)ntask);
+    }
+    __syncthreads();
+    if (ntask) {
+        const unsigned long long pos = uni64(L.pos);
+        for (uint32_t b = tid; b < nb; b += NT)
+            if (L.kind[b] == 1)
+                seed_task(P, pos + L.rk[b], Task{g.begin + L.bst[b], L.cnt[b], child_depth(sp, h, b), cpar, g.setbase});
+    }
+    __syncthreads();
     // small list and chunks
-    for (uint32_t b = tid; b < NBPAD; b += NT) L.psz[b] = (b < nb && L.kind[b] == 2) ? 1u : 0u;
+    uint32_t *psz = L.rk;
+    for (uint32_t b = tid; b < nb; b += NT) psz[b] = L.kind[b] == 2 ? 1u : 0u;
     __syncthreads();
-    const uint32_t nsmall = uni(block_scan(L.psz, (int)nb, L.tmp, true, AddOp(), 0u));
+    const uint32_t nsmall = uni(block_scan(psz, (int)nb, L.tmp, true, AddOp(), 0u));
     for (uint32_t b = tid; b < nb; b += NT)
-        if (L.kind[b] == 2) L.lsmall[L.psz[b]] = (uint16_t)b;
+        if (L.kind[b] == 2) L.lsmall[psz[b]] = (uint16_t)b;
     __syncthreads();
-    for (uint32_t k = tid; k < nsmall; k += NT) L.psz[k] = L.cnt[L.lsmall[k]];
+    for (uint32_t k = tid; k < nsmall; k += NT) psz[k] = L.cnt[L.lsmall[k]];
     __syncthreads();
-    const uint32_t small_total = block_scan(L.psz, (int)nsmall, L.tmp, true, AddOp(), 0u);
+    const uint32_t small_total = block_scan(psz, (int)nsmall, L.tmp, true, AddOp(), 0u);
     if (tid == 0) {
-        L.psz[nsmall] = small_total;
+        psz[nsmall] = small_total;
         L.nchunk = 0;
     }
     __syncthreads();
     const uint32_t cap = (P.tbase * 2 <= P.chunk) ? P.chunk - P.tbase : 0u;
     for (uint32_t k = tid; k < nsmall; k += NT) {
-        const uint32_t ck = cap ? L.psz[k] / cap : k;
-        const uint32_t cp = k ? (cap ? L.psz[k - 1] / cap : k - 1) : 0xFFFFFFFFu;
+        const uint32_t ck = cap ? psz[k] / cap : k;
+        const uint32_t cp = k ? (cap ? psz[k - 1] / cap : k - 1) : 0xFFFFFFFFu;
         if (ck != cp) L.cfirst[ck] = (uint16_t)k;
         if (k == nsmall - 1) L.nchunk = ck + 1;
     }
@@ -1590,10 +1609,9 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
     const uint32_t nchunk = uni(L.nchunk);
     if (tid == 0) {
         L.cfirst[nchunk] = (uint16_t)nsmall;
-        const unsigned long long nt = (unsigned long long)ntask + nchunk;
-        if (nt) {
-            add_agent(&P.ctl->pending, nt);
-            L.pos = add_agent(&P.ctl->tail, nt);
+        if (nchunk) {
+            add_agent(&P.ctl->pending, (unsigned long long)nchunk);
+            L.pos = add_agent(&P.ctl->tail, (unsigned long long)nchunk);
         }
         L.db = nsmall ? add_agent(&P.ctl->desc_top, (unsigned long long)nsmall) : 0ull;
         if (L.db + nsmall > P.desc_cap) atomicOr(&P.ctl->error, ERR_DESC_CAP);
@@ -1601,19 +1619,39 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
     __syncthreads();
     const unsigned long long pos = uni64(L.pos), db = uni64(L.db);
     if (db + nsmall > P.desc_cap) return;
-    for (uint32_t b = tid; b < nb; b += NT)
-        if (L.kind[b] == 1)
-            seed_task(P, pos + L.rk[b],
-                      Task{g.begin + L.bst[b], L.cnt[b], child_depth(L.sp, h, b), cpar, g.setbase});
     for (uint32_t k = tid; k < nsmall; k += NT) {
         const uint32_t b = L.lsmall[k];
-        P.desc[db + k] = GroupDesc{g.begin + L.bst[b], L.cnt[b], child_depth(L.sp, h, b), 0u};
+        P.desc[db + k] = GroupDesc{g.begin + L.bst[b], L.cnt[b], child_depth(sp, h, b), 0u};
     }
     for (uint32_t c = tid; c < nchunk; c += NT) {
         const uint32_t k0 = L.cfirst[c], k1 = L.cfirst[c + 1];
-        seed_task(P, pos + ntask + c,
-                  Task{(uint32_t)(db + k0), k1 - k0, L.psz[k1] - L.psz[k0], M_CHUNK | cpar, g.setbase});
+        seed_task(P, pos + c, Task{(uint32_t)(db + k0), k1 - k0, psz[k1] - psz[k0], M_CHUNK | cpar, g.setbase});
     }
+}
+
+struct LvlSchedLDS {
+    Split sp;
+    SchedLDS<NBPAD> s;
+};
+
+// A level's segment: bucket sizes from the column scan's totals, starts by a
+// prefix sum over them.
+__global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
+    __shared__ LvlSchedLDS L;
+    if (P.ctl->error || blockIdx.x >= lvl_count(P, l, 0)) return;
+    const int tid = threadIdx.x;
+    const LvlSeg g = P.lseg[l][blockIdx.x];
+    load_split(L.sp, &P.lsplit[l][blockIdx.x]);
+    const uint32_t nb = uni(L.sp.nb);
+    const uint32_t *tot = &P.ltot[l][(size_t)blockIdx.x * NBPAD];
+    for (uint32_t b = tid; b < NBPAD; b += NT) {
+        const uint32_t c = b < nb ? tot[b] : 0u;
+        L.s.cnt[b] = c;
+        L.s.bst[b] = c;
+    }
+    __syncthreads();
+    block_scan(L.s.bst, (int)nb, L.s.tmp, true, AddOp(), 0u);
+    schedule_buckets<NBPAD>(P, l, g, nb, L.sp, L.s);
 }
 
 // ---------------------------------------------------------------------------

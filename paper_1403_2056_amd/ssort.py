@@ -126,7 +126,7 @@ _SIGS = {
     "ssort_debug_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                        ctypes.c_size_t, ctypes.c_void_p]),
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
 }
 
 
@@ -345,22 +345,23 @@ class Sorter:
         dev = f"cuda:{self.device}"
         n = s.n
         keys = torch.empty(n, dtype=torch.int64, device=dev)
-        split = torch.empty(256, dtype=torch.int64, device=dev)
-        tree = torch.empty(256, dtype=torch.int64, device=dev)
+        split = torch.empty(4096, dtype=torch.int64, device=dev)
+        tree = torch.empty(4096, dtype=torch.int64, device=dev)
+        jump = torch.zeros(4096, dtype=torch.int16, device=dev)
         info = torch.empty(4, dtype=torch.int32, device=dev)
         bucket = torch.empty(n, dtype=torch.int16, device=dev)
-        hist = torch.empty(512, dtype=torch.int32, device=dev)
+        hist = torch.empty(8192, dtype=torch.int32, device=dev)
         perm = torch.empty(n, dtype=torch.int32, device=dev)
         ws = self.workspace(n)
         st = s.struct()
         _check(lib().ssort_debug_step(self._h, ctypes.byref(st), depth, _ptr(keys), _ptr(split), _ptr(tree),
-                                      _ptr(info), _ptr(bucket), _ptr(hist), _ptr(perm), _ptr(ws), ws.numel(),
-                                      _stream(stream)), "ssort_debug_step")
+                                      _ptr(jump), _ptr(info), _ptr(bucket), _ptr(hist), _ptr(perm), _ptr(ws),
+                                      ws.numel(), _stream(stream)), "ssort_debug_step")
         torch.cuda.synchronize()
         out = {"keys": keys.cpu().numpy().view(np.uint64), "split": split.cpu().numpy().view(np.uint64),
                "tree": tree.cpu().numpy().view(np.uint64), "info": info.cpu().numpy().view(np.uint32),
                "bucket": bucket.cpu().numpy().view(np.uint16), "hist": hist.cpu().numpy().view(np.uint32),
-               "perm": perm.cpu().numpy().view(np.uint32)}
+               "perm": perm.cpu().numpy().view(np.uint32), "jump": jump.cpu().numpy().view(np.uint16)}
         v = int(out["info"][0])
         out["split"] = out["split"][:v]
         out["tree"] = out["tree"][:v]
