@@ -134,8 +134,9 @@ typedef struct {
      * tree, 2 classify and count, 3 redistribution, 4 child scheduling and
      * identical buckets, 5 base case (loading and writing the chunk),
      * 6 common-prefix extension of a segment, 7 other, 8 base-case prefix
-     * extension, 9 base-case key gathers, 10 base-case ranking and class
-     * splitting, 11 the last wait (for the queue to drain), 12-15 unused */
+     * extension, 9 base-case key gathers, 10 base-case ranking, 11 the last
+     * wait (for the queue to drain), 12 base-case class splitting, 13-15
+     * unused */
     uint64_t phase_ticks[16];
     uint64_t base_chunks;
     uint64_t base_rounds;
@@ -296,6 +297,29 @@ ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t 
                               uint64_t *keys, uint64_t *split, uint64_t *tree, uint16_t *jump,
                               uint32_t *info, uint16_t *bucket, uint32_t *hist, uint32_t *perm, void *ws,
                               size_t ws_bytes, void *stream);
+
+/* ---- one segment step of the persistent worker with its intermediates ----
+ * Runs the step a worker applies to a segment (Algorithm 1 on one segment by
+ * one workgroup: sample and splitters, the exact common-prefix extension when
+ * every sampled key is equal, classification, count, prefix sum, stable
+ * redistribution, scheduling of the children) on all n strings of `in` as one
+ * segment at common depth `depth`; the children are not run.  Outputs (device):
+ *  split         uint64[256]  sorted splitters x_0..x_{v'-1}
+ *  info          uint32[4]    {v', d', distinct sample keys, depth h of the
+ *                             classification (>= depth after an extension)}
+ *  splitter_lcp  uint32[256]  h'[l] = lcp of x_{l-1} and x_l in bytes (at most
+ *                             8), h'[0] = h'[v'] = 0
+ *  ends          uint32[256]  1 where x_l ends its string (last byte zero)
+ *  bucket_start, bucket_size, child_depth  uint32[512]: per bucket 0..2v',
+ *                             its first position in the redistributed order,
+ *                             its size, and the common prefix length its
+ *                             strings are recursed with (Algorithm 1's output)
+ *  perm          uint32[n]    input indices after the stable redistribution
+ * Byte keys whatever the tuning's flags.  ws as for ssort_sort with n strings. */
+ssort_status ssort_debug_segment_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t depth, uint64_t *split,
+                                      uint32_t *info, uint32_t *splitter_lcp, uint32_t *ends, uint32_t *bucket_start,
+                                      uint32_t *bucket_size, uint32_t *child_depth, uint32_t *perm, void *ws,
+                                      size_t ws_bytes, void *stream);
 
 /* ---- graph-captured launch (the batched form) ----
  * Capture one sort (set_begin == NULL: ssort_sort of `in`; else

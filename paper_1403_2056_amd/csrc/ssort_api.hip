@@ -653,6 +653,42 @@ ssort_status ssort_debug_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t 
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
 }
 
+ssort_status ssort_debug_segment_step(ssort_ctx *ctx, const ssort_strings *in, uint32_t depth, uint64_t *split,
+                                      uint32_t *info, uint32_t *splitter_lcp, uint32_t *ends, uint32_t *bucket_start,
+                                      uint32_t *bucket_size, uint32_t *child_depth, uint32_t *perm, void *ws,
+                                      size_t ws_bytes, void *stream) {
+    if (!ctx) return SSORT_EINVAL;
+    ssort_status st = check_strings(in);
+    if (st != SSORT_OK) return st;
+    if (in->n == 0 || !split || !info || !splitter_lcp || !ends || !bucket_start || !bucket_size || !child_depth ||
+        !perm || !ws)
+        return SSORT_EINVAL;
+    const Layout L = layout(ctx, in->n, 1);
+    if (ws_bytes < L.total) return SSORT_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SSORT_EDEVICE;
+    Params P = make_params(ctx, in, perm, nullptr, ws, L, 1, nullptr);
+    P.alpha = nullptr;   // byte keys
+    hipLaunchKernelGGL(k_init, dim3(grid_for(L.cap)), dim3(NT), 0, s, P, (unsigned long long)L.cap);
+    const int C = chunk_for(ctx->tun.base_threshold);
+    const dim3 g(1), b(NT);
+    if (ctx->tun.keys_per_thread == 4 && C == 512)
+        hipLaunchKernelGGL((k_debug_segstep<4, 512, false>), g, b, 0, s, P, depth, split, info, splitter_lcp, ends,
+                           bucket_start, bucket_size, child_depth);
+    else if (ctx->tun.keys_per_thread == 4)
+        hipLaunchKernelGGL((k_debug_segstep<4, 1024, false>), g, b, 0, s, P, depth, split, info, splitter_lcp, ends,
+                           bucket_start, bucket_size, child_depth);
+    else if (C == 512)
+        hipLaunchKernelGGL((k_debug_segstep<8, 512, false>), g, b, 0, s, P, depth, split, info, splitter_lcp, ends,
+                           bucket_start, bucket_size, child_depth);
+    else
+        hipLaunchKernelGGL((k_debug_segstep<8, 1024, false>), g, b, 0, s, P, depth, split, info, splitter_lcp, ends,
+                           bucket_start, bucket_size, child_depth);
+    hipLaunchKernelGGL(k_debug_perm, dim3(grid_for(in->n)), dim3(NT), 0, s, P, perm);
+    ctx->last_ws = ws;
+    return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
+}
+
 struct ssort_graph {
     hipGraph_t graph;
     hipGraphExec_t exec;

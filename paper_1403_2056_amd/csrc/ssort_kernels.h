@@ -50,7 +50,7 @@ enum {
 // worker phases timed on the device
 enum { PH_WAIT = 0, PH_SAMPLE = 1, PH_CLASSIFY = 2, PH_SCATTER = 3, PH_CHILDREN = 4, PH_BASE = 5,
        PH_EXTEND = 6, PH_OTHER = 7, PH_BEXT = 8, PH_BKEY = 9, PH_BRANK = 10,
-       PH_DRAIN = 11 };
+       PH_DRAIN = 11, PH_BSPLIT = 12 };
 
 // Device error bits (the mask reads back through the statistics): input
 // errors, the wait limit, and one bit per internal consistency check, each of

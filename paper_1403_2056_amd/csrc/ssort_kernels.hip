@@ -478,6 +478,7 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
             }
         }
         __syncthreads();
+        mk(PH_BRANK);
         cur ^= 1;
         more = uni(B.any) != 0;
         if (more) {
@@ -492,7 +493,7 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
         }
         __syncthreads();
         if (tid == 0) B.any = 0;
-        mk(PH_BRANK);
+        mk(PH_BSPLIT);
     }
     for (uint32_t q = tid; q < M; q += NT) P.perm[gpos(q)] = B.id[B.ord[cur][q]] - setbase;
     if (tid == 0) {
@@ -529,6 +530,7 @@ struct StepLDS {
     unsigned long long st[NST];   // this workgroup's statistics (thread 0)
     unsigned long long ph_last;
     uint32_t ext_min, nlist;
+    uint32_t hstep;               // depth of the last step's classification (after any extension)
     uint32_t tmp[NW];
     union {
         struct {
@@ -739,6 +741,7 @@ __device__ __forceinline__ bool seg_step(const Params &P, Task &t, StepLDS<K, C>
         L.st[ST_SEGMENTS] += 1;
         L.st[ST_STRINGS] += S;
         L.st[ST_MAX_DEPTH] = max(L.st[ST_MAX_DEPTH], (unsigned long long)h);
+        L.hstep = h;
     }
     __syncthreads();
     const uint32_t nb = uni(L.sp.nb);
@@ -1749,6 +1752,48 @@ __global__ void k_debug_dump(Params P, uint32_t depth, uint64_t *keys, uint64_t 
     }
 }
 
+// Debug: one segment step of the persistent worker (sample, any common-prefix
+// extension, classification, count, prefix sum, redistribution, children) on
+// the whole input as one segment at `depth`, by one workgroup, then its
+// splitters, splitter LCPs, end flags, classification depth and every
+// bucket's start, size and child depth.  The children it queues are never
+// run; its small buckets are not sorted.
+template <int K, int C, bool Z>
+__global__ __launch_bounds__(NT) void k_debug_segstep(Params P, uint32_t depth, uint64_t *split, uint32_t *info,
+                                                      uint32_t *hl, uint32_t *zr, uint32_t *bst, uint32_t *bsz,
+                                                      uint32_t *bdep) {
+    __shared__ StepLDS<K, C> L;
+    if (threadIdx.x < NPH) L.ph[threadIdx.x] = 0;
+    if (threadIdx.x < NST) L.st[threadIdx.x] = 0;
+    if (threadIdx.x == 0) L.ph_last = wall_clock64();
+    __syncthreads();
+    Task t{0, P.S.n, depth, M_IDENT_SRC, 0};
+    seg_step<K, C>(P, t, L, KeyOf<Z>::make(P), false);
+    __syncthreads();
+    const uint32_t v = L.sp.v, nb = L.sp.nb, h = L.hstep;
+    for (uint32_t j = threadIdx.x; j < (uint32_t)(VMAX + 1); j += NT) {
+        split[j] = j < v ? splitter(L.sp, j) : 0;
+        hl[j] = j <= v ? L.sp.hl[j] : 0;
+        zr[j] = j < v ? L.sp.zr[j] : 0;
+    }
+    for (uint32_t b = threadIdx.x; b < (uint32_t)NBPAD; b += NT) {
+        bst[b] = b < nb ? L.bst[b] : 0;
+        bsz[b] = b < nb ? L.hist[b] : 0;
+        bdep[b] = b < nb ? child_depth(L.sp, h, b) : 0;
+    }
+    if (threadIdx.x == 0) {
+        info[0] = v;
+        info[1] = L.sp.d;
+        info[2] = L.sp.ndistinct;
+        info[3] = h;
+    }
+}
+
+// Debug: the permutation after a segment step (its records are in R1).
+__global__ void k_debug_perm(Params P, uint32_t *perm) {
+    for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < P.S.n; i += gridDim.x * NT) perm[i] = P.R1[i].id;
+}
+
 // Packing of a server batch: job k's strings are rows set_begin[k] ..
 // set_begin[k+1] of the flat space; its characters start at char_base and its
 // raw offsets (CSR n+1, or n starts for suffixes of its text) at raw_base.
@@ -1782,6 +1827,14 @@ template __global__ void k_worker<4, 512, true>(Params);
 template __global__ void k_worker<4, 1024, true>(Params);
 template __global__ void k_worker<8, 512, true>(Params);
 template __global__ void k_worker<8, 1024, true>(Params);
+template __global__ void k_debug_segstep<4, 512, false>(Params, uint32_t, uint64_t *, uint32_t *, uint32_t *,
+                                                        uint32_t *, uint32_t *, uint32_t *, uint32_t *);
+template __global__ void k_debug_segstep<4, 1024, false>(Params, uint32_t, uint64_t *, uint32_t *, uint32_t *,
+                                                         uint32_t *, uint32_t *, uint32_t *, uint32_t *);
+template __global__ void k_debug_segstep<8, 512, false>(Params, uint32_t, uint64_t *, uint32_t *, uint32_t *,
+                                                        uint32_t *, uint32_t *, uint32_t *, uint32_t *);
+template __global__ void k_debug_segstep<8, 1024, false>(Params, uint32_t, uint64_t *, uint32_t *, uint32_t *,
+                                                         uint32_t *, uint32_t *, uint32_t *, uint32_t *);
 template __global__ void k_lvl_sample<false>(Params, uint32_t);
 template __global__ void k_lvl_sample<true>(Params, uint32_t);
 template __global__ void k_lvl_classify<4, false>(Params, uint32_t);

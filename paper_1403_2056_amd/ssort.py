@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
 
 
 PHASES = ["wait", "sample", "classify", "scatter", "children", "base", "extend", "other",
-          "base_extend", "base_keys", "base_rank", "drain"]
+          "base_extend", "base_keys", "base_rank", "drain", "base_split"]
 
 
 class Job(ctypes.Structure):
@@ -127,6 +127,8 @@ _SIGS = {
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "ssort_debug_segment_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Strings), ctypes.c_uint32]
+                                 + [ctypes.c_void_p] * 9 + [ctypes.c_size_t, ctypes.c_void_p]),
 }
 
 
@@ -367,6 +369,37 @@ class Sorter:
         out["tree"] = out["tree"][:v]
         out["hist"] = out["hist"][:2 * v + 1]
         return out
+
+
+    def debug_segment_step(self, s: DeviceStrings, depth: int = 0, stream=None) -> dict:
+        """One persistent-worker segment step on the whole input: splitters,
+        splitter LCPs, end flags, classification depth, per-bucket start, size
+        and child depth, and the redistributed permutation (host arrays)."""
+        torch = self._torch
+        dev = f"cuda:{self.device}"
+        n = s.n
+        u32 = dict(dtype=torch.int32, device=dev)
+        split = torch.empty(256, dtype=torch.int64, device=dev)
+        info = torch.empty(4, **u32)
+        hl = torch.empty(256, **u32)
+        zr = torch.empty(256, **u32)
+        bst = torch.empty(512, **u32)
+        bsz = torch.empty(512, **u32)
+        bdep = torch.empty(512, **u32)
+        perm = torch.empty(n, **u32)
+        ws = self.workspace(n)
+        st = s.struct()
+        _check(lib().ssort_debug_segment_step(self._h, ctypes.byref(st), depth, _ptr(split), _ptr(info), _ptr(hl),
+                                              _ptr(zr), _ptr(bst), _ptr(bsz), _ptr(bdep), _ptr(perm), _ptr(ws),
+                                              ws.numel(), _stream(stream)), "ssort_debug_segment_step")
+        torch.cuda.synchronize()
+        info = info.cpu().numpy().view(np.uint32)
+        v = int(info[0])
+        nb = 2 * v + 1
+        return {"split": split.cpu().numpy().view(np.uint64)[:v], "info": info,
+                "hl": hl.cpu().numpy().view(np.uint32)[: v + 1], "zr": zr.cpu().numpy().view(np.uint32)[:v],
+                "start": bst.cpu().numpy().view(np.uint32)[:nb], "size": bsz.cpu().numpy().view(np.uint32)[:nb],
+                "depth": bdep.cpu().numpy().view(np.uint32)[:nb], "perm": perm.cpu().numpy().view(np.uint32)}
 
 
 class Graph:
