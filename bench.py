@@ -36,7 +36,7 @@ WORKLOAD_TEXT = {
 
 # the files that define the sort's kernels and their launches (the merge and
 # the server are host code and kernels of their own, outside the profiled sort)
-SORT_SOURCES = ("ssort_dev.h", "ssort_kernels.h", "ssort_kernels.hip", "ssort_api.hip")
+SORT_SOURCES = ("ssort_dev.h", "ssort_kernels.h", "ssort_kernels.hip", "ssort_wide.hip", "ssort_api.hip")
 
 
 def source_hash() -> str:
@@ -338,6 +338,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5, help="timed graph launches of the batched block")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a device copy of this many GiB (counter scaling runs)")
+    ap.add_argument("--gather-probe-m", type=int, default=0,
+                    help="also gather this many random 8-byte words from a 1 GiB table (counter scaling runs)")
     ap.add_argument("--v", type=int, default=255)
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--tb", type=int, default=128)
@@ -409,6 +411,16 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
+    if args.gather_probe_m > 0:
+        # random 8-byte reads of known count: index_select reads the indices
+        # in order, one table word per index at random, writes the words in order
+        table = torch.zeros(1 << 27, dtype=torch.int64, device="cuda")
+        idx = torch.randint(0, 1 << 27, (args.gather_probe_m,), dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        g = torch.index_select(table, 0, idx)
+        torch.cuda.synchronize()
+        del table, idx, g
 
     p = perm.cpu().numpy().view(np.uint32)
     h = lcp.cpu().numpy().view(np.uint32)

@@ -321,6 +321,22 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
     return x;
 }
 
+// Position of sample t of a (< size) in a segment of `size` strings: one
+// pseudo-random pick in each of a strata of size / a strings (every string
+// when the segment holds at most a; the last size mod a strings are never
+// picked).  32-bit arithmetic only.
+__device__ __forceinline__ uint32_t sample_pos(uint32_t t, uint32_t a, uint32_t size, uint32_t seed) {
+    if (size <= a) return t;
+    const uint32_t stride = size / a;
+    return t * stride + hash32(seed ^ (t * 0x9E3779B9u)) % stride;
+}
+
+// Sample size for a segment of `size` strings: ovs (v + 1) - 1, at most size.
+__device__ __forceinline__ uint32_t sample_count(uint32_t size, uint32_t vmax, uint32_t ovs) {
+    const uint32_t amax = ovs * (vmax + 1) - 1;
+    return size < amax ? size : amax;
+}
+
 // Sample keys and splitters for a segment of `size` strings at depth h, read
 // through `load(e)` (0 <= e < size).  Sample of up to ovs(v+1)-1 keys
 // (oversampling factor ovs; all strings when the segment is that small, else
@@ -337,16 +353,8 @@ __device__ __forceinline__ void select_splitters(SP &sp, uint32_t size, uint32_t
                                                  uint32_t equal, uint64_t *samp, uint64_t *srt, uint32_t *fl,
                                                  uint32_t *tmp, Load load, const KC &kc, uint32_t ovs = 2) {
     const int tid = tid_here();
-    const uint32_t amax = ovs * (vmax + 1) - 1;
-    const uint32_t a = size < amax ? size : amax;
-    const bool all = size <= a;
-    const uint32_t stride = all ? 1u : size / a;
-    for (uint32_t t = tid; t < a; t += NT) {
-        uint32_t pos;
-        if (all) pos = t;
-        else pos = (uint32_t)(((uint64_t)t * size) / a) + hash32(seed ^ (t * 0x9E3779B9u)) % stride;
-        samp[t] = load(pos, h);
-    }
+    const uint32_t a = sample_count(size, vmax, ovs);
+    for (uint32_t t = tid; t < a; t += NT) samp[t] = load(sample_pos(t, a, size, seed), h);
     // sort the sample: bitonic network over the next power of two, padded
     // with the largest key (padding sorts last, so srt[0..a) holds the sample)
     uint32_t a2 = 1;

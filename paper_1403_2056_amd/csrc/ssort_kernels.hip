@@ -287,6 +287,7 @@ struct BaseLDS {
     uint32_t d[C];           // per element: class depth, or DONE
     uint32_t scr[C];
     uint32_t cls[C];         // per position: class start | class end << 16
+    uint32_t gp[C];          // per position: its place in the output arrays
     uint16_t ord[2][C];      // element at each position
     uint32_t any;
     uint32_t nlist;
@@ -306,10 +307,6 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
             if (grp.gpre(mid) <= q) lo = mid; else hi = mid;
         }
         return lo;
-    };
-    auto gpos = [&](uint32_t q) -> uint32_t {
-        const uint32_t g = find(q);
-        return grp.gstart(g) + (q - grp.gpre(g));
     };
     constexpr int PER = (C + NT - 1) / NT;   // positions per thread
     const unsigned long long t_start = wall_clock64();
@@ -335,6 +332,7 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
             B.id[q] = rr[u].id;
             B.d[q] = sz >= 2 ? grp.gdepth(g) : DONE;
             B.cls[q] = c0 | ((c0 + sz) << 16);
+            B.gp[q] = grp.gstart(g) + (q - c0);
             B.ord[0][q] = (uint16_t)q;
         }
     }
@@ -430,52 +428,68 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
         }
         __syncthreads();
         mk(PH_BKEY);
-        // rank inside the class; the key run's first element also finds the
-        // largest smaller key (its new predecessor) for the lcp
+        // rank inside the class by (key, position): the keys below, plus the
+        // equal keys at earlier positions (positions inside a class follow
+        // input order: every redistribution and round is stable)
         {
             uint32_t np[PER];
+            uint64_t kk[PER];
             bool on[PER];
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const uint32_t q = tid + u * NT;
                 on[u] = false;
-                if (q >= M) continue;
-                const uint32_t e = B.ord[cur][q];
                 np[u] = q;
-                if (B.d[e] == DONE) continue;
+                if (q >= M) continue;
+                if (B.d[B.ord[cur][q]] == DONE) continue;
                 on[u] = true;
                 const uint32_t cl = B.cls[q], c0 = cl & 0xFFFF, c1 = cl >> 16;
                 const uint64_t k = B.kq[q];
-                uint32_t less = 0, eqb = 0, eqa = 0;
-                uint64_t ml = 0;
+                kk[u] = k;
+                uint32_t r = 0;
                 for (uint32_t j = c0; j < c1; ++j) {
                     const uint64_t kj = B.kq[j];
-                    const bool lt = kj < k, eq = kj == k;
-                    less += lt ? 1u : 0u;
-                    eqa += eq ? 1u : 0u;
-                    eqb += (eq && j < q) ? 1u : 0u;
-                    ml = (lt && kj > ml) ? kj : ml;
+                    r += (j < q ? kj <= k : kj < k) ? 1u : 0u;
                 }
-                np[u] = c0 + less + eqb;
-                const uint32_t de = B.d[e];
-                if (eqb == 0) {
-                    if (less && P.lcp) P.lcp[gpos(np[u])] = de + kc.eqc(k ^ ml);
-                } else if (kc.ends(k)) {
-                    if (P.lcp) P.lcp[gpos(np[u])] = B.ln[e];
-                }
-                const bool go = eqa >= 2 && !kc.ends(k);
-                B.d[e] = go ? de + kc.q() : DONE;
-                if (go) B.any = 1;
-                // a run's first element marks a new class start
-                B.scr[np[u]] = eqb == 0 ? np[u] : 0u;
+                np[u] = c0 + r;
             }
+            __syncthreads();
+            // keys and elements at their new positions (a class keeps its
+            // positions; finished elements stay where they are)
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const uint32_t q = tid + u * NT;
                 if (q >= M) continue;
-                if (!on[u]) B.scr[q] = q;
                 B.ord[cur ^ 1][np[u]] = B.ord[cur][q];
+                if (on[u]) B.kq[np[u]] = kk[u];
             }
+        }
+        __syncthreads();
+        // runs of equal keys in the new order: a run's first element gets its
+        // lcp with the largest smaller key of its class (its new predecessor),
+        // equal keys that end their strings are identical strings (lcp =
+        // length), runs of two or more without an end stay active 8
+        // characters deeper; each run start begins a class
+        for (uint32_t p = tid; p < M; p += NT) {
+            const uint32_t e = B.ord[cur ^ 1][p];
+            const uint32_t de = B.d[e];
+            if (de == DONE) {
+                B.scr[p] = p;
+                continue;
+            }
+            const uint32_t cl = B.cls[p], c0 = cl & 0xFFFF, c1 = cl >> 16;
+            const uint64_t k = B.kq[p];
+            const bool first = p == c0 || B.kq[p - 1] != k;
+            const bool last = p + 1 == c1 || B.kq[p + 1] != k;
+            if (first) {
+                if (p > c0 && P.lcp) P.lcp[B.gp[p]] = de + kc.eqc(k ^ B.kq[p - 1]);
+            } else if (kc.ends(k)) {
+                if (P.lcp) P.lcp[B.gp[p]] = B.ln[e];
+            }
+            const bool go = !(first && last) && !kc.ends(k);
+            B.d[e] = go ? de + kc.q() : DONE;
+            if (go) B.any = 1;
+            B.scr[p] = first ? p : 0u;
         }
         __syncthreads();
         mk(PH_BRANK);
@@ -495,7 +509,7 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
         if (tid == 0) B.any = 0;
         mk(PH_BSPLIT);
     }
-    for (uint32_t q = tid; q < M; q += NT) P.perm[gpos(q)] = B.id[B.ord[cur][q]] - setbase;
+    for (uint32_t q = tid; q < M; q += NT) P.perm[B.gp[q]] = B.id[B.ord[cur][q]] - setbase;
     if (tid == 0) {
         const unsigned long long dt = wall_clock64() - t_start;
         st[ST_CHUNKS] += 1;
@@ -1069,8 +1083,12 @@ template <> struct KeyOf<true> {
     }
 };
 
+#ifndef SSD_WORKER_OCC
+#define SSD_WORKER_OCC 4
+#endif
+
 template <int K, int C, bool Z>
-__global__ __launch_bounds__(NT, 4) void k_worker(Params P) {
+__global__ __launch_bounds__(NT, SSD_WORKER_OCC) void k_worker(Params P) {
     __shared__ StepLDS<K, C> L;
     __shared__ unsigned long long claim;
     __shared__ int outcome;
