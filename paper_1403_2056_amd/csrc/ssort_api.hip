@@ -108,8 +108,11 @@ Layout layout(const ssort_ctx *c, uint32_t n, uint32_t m) {
     // the slot is reused
     const uint32_t wv = wide_v(c->tun);
     const uint64_t nb0 = wv ? 2 * (uint64_t)wv + 1 : (uint64_t)NBMAX;   // buckets of a level-0 segment
+    // (level-0 segments: at most one per set; their chunks of small buckets
+    // never span more than one scheduling workgroup's buckets)
+    const uint64_t seg0 = std::min<uint64_t>(m, L.maxseg);
     const uint64_t live = 2 * (uint64_t)n / (c->tun.base_threshold + 1) + (uint64_t)n / 128 + m +
-                          (nb0 + NBMAX) * (L.maxseg + 1) + (uint64_t)c->worker_blocks;
+                          (nb0 + 16) * seg0 + (uint64_t)NBMAX * (L.maxseg + 1) + (uint64_t)c->worker_blocks;
     L.cap = next_pow2(2 * live + 1024);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -237,7 +240,7 @@ void launch_wide_level(const ssort_ctx *c, const Params &P, const Layout &L, boo
     if (K == 4) hipLaunchKernelGGL((k_wscatter<4, 2>), tiles, b, 0, s, P, hb);
     else hipLaunchKernelGGL((k_wscatter<8, 2>), tiles, b, 0, s, P, hb);
     hipLaunchKernelGGL(k_wbounds, tiles, b, 0, s, P);
-    if (schedule) hipLaunchKernelGGL(k_wschedule, dim3(L.maxseg), b, 0, s, P);
+    if (schedule) hipLaunchKernelGGL(k_wschedule, dim3(L.maxseg * WSCHED_G), b, 0, s, P);
 }
 
 void launch_levels(const ssort_ctx *c, const Params &P, const Layout &L, bool schedule, hipStream_t s) {

@@ -20,7 +20,10 @@ constexpr int NBMAX = 2 * VMAX + 1;     // 511 buckets
 constexpr int NBPAD = 512;
 constexpr int SAMPLE_MAX = 2 * (VMAX + 1) - 1;   // oversampling factor 2
 constexpr int CH = 1024;                // base-case chunk (strings held in LDS)
-constexpr int ROOT_CHUNKS = 8;          // chunks of NT*K strings per whole-GPU root-step tile
+#ifndef SSD_ROOT_CHUNKS
+#define SSD_ROOT_CHUNKS 4
+#endif
+constexpr int ROOT_CHUNKS = SSD_ROOT_CHUNKS;   // chunks of NT*K strings per whole-GPU level tile
 constexpr uint32_t SEAM = 0x80000000u;  // lcp slot still holds a separation depth
 constexpr uint32_t TO_END = 1u;
 
@@ -347,13 +350,15 @@ __device__ __forceinline__ uint32_t sample_count(uint32_t size, uint32_t vmax, u
 // tree, the splitter LCPs (xor + count leading zeros) and the end-of-string
 // flags.  `samp`, `srt` need ovs(vmax+1) entries (a power of two: the sort
 // pads to one), `fl` as many, tmp NW.  SP is Split, or the wide level's
-// WSplit (same fields, larger arrays).
-template <typename SP, typename Load, typename KC>
+// WSplit (same fields, larger arrays).  UNR: sample loads issued together per
+// thread (the persistent worker keeps 1 for its code size).
+template <int UNR = 1, typename SP, typename Load, typename KC>
 __device__ __forceinline__ void select_splitters(SP &sp, uint32_t size, uint32_t h, uint32_t seed, uint32_t vmax,
                                                  uint32_t equal, uint64_t *samp, uint64_t *srt, uint32_t *fl,
                                                  uint32_t *tmp, Load load, const KC &kc, uint32_t ovs = 2) {
     const int tid = tid_here();
     const uint32_t a = sample_count(size, vmax, ovs);
+#pragma unroll UNR
     for (uint32_t t = tid; t < a; t += NT) samp[t] = load(sample_pos(t, a, size, seed), h);
     // sort the sample: bitonic network over the next power of two, padded
     // with the largest key (padding sorts last, so srt[0..a) holds the sample)

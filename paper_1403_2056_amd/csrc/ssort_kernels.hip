@@ -1545,14 +1545,15 @@ struct SchedLDS {
     uint32_t tmp[NW];
 };
 
-// Children of a level's segment, once its bucket sizes and starts are in
-// L.cnt / L.bst: the next level's segments, worker tasks for the other large
-// buckets, identical strings finished here, and the small buckets as
-// base-case chunk tasks (group descriptors, chunks of at most C - threshold
-// strings, never splitting a group).  SP (Split or WSplit, in LDS or device
-// memory) gives the end-of-string flags and splitter LCPs.
+// Children of buckets b0 .. b0 + nb - 1 of a level's segment, once their
+// sizes and starts are in L.cnt / L.bst (indexed from b0): the next level's
+// segments, worker tasks for the other large buckets, identical strings
+// finished here, and the small buckets as base-case chunk tasks (group
+// descriptors, chunks of at most C - threshold strings, never splitting a
+// group).  SP (Split or WSplit, in LDS or device memory) gives the
+// end-of-string flags and splitter LCPs.
 template <int NBC, typename SP>
-__device__ void schedule_buckets(const Params &P, uint32_t l, const LvlSeg &g, uint32_t nb, const SP &sp,
+__device__ void schedule_buckets(const Params &P, uint32_t l, const LvlSeg &g, uint32_t b0, uint32_t nb, const SP &sp,
                                  SchedLDS<NBC> &L) {
     const int tid = threadIdx.x;
     const uint32_t h = g.depth;
@@ -1562,7 +1563,8 @@ __device__ void schedule_buckets(const Params &P, uint32_t l, const LvlSeg &g, u
         const uint32_t c = L.cnt[b];
         uint32_t kind = 0;
         if (c) {
-            const bool ident = (b & 1) && sp.zr[b >> 1];
+            const uint32_t gb = b0 + b;
+            const bool ident = (gb & 1) && sp.zr[gb >> 1];
             if (ident) kind = 3;
             else if (!(c > LVL_MIN && l + 1 < LMAX)) kind = c > P.tbase ? 1u : 2u;
         }
@@ -1577,11 +1579,11 @@ __device__ void schedule_buckets(const Params &P, uint32_t l, const LvlSeg &g, u
         if (!c) continue;
         if (P.lcp && st > 0) P.lcp[g.begin + st] = SEAM | h;
         if (L.kind[b] == 0)
-            lvl_append(P, l + 1, LvlSeg{g.begin + st, c, child_depth(sp, h, b), cpar, 0, 0, g.setbase, 0});
+            lvl_append(P, l + 1, LvlSeg{g.begin + st, c, child_depth(sp, h, b0 + b), cpar, 0, 0, g.setbase, 0});
     }
     // identical strings (an equality bucket whose splitter ends the string):
     // already in input order, lcp = length
-    for (uint32_t b = 1; b < nb; b += 2) {
+    for (uint32_t b = (b0 & 1) ? 0u : 1u; b < nb; b += 2) {
         if (uni(L.kind[b]) != 3) continue;
         const uint32_t c = L.cnt[b], st = g.begin + L.bst[b];
         for (uint32_t i = tid; i < c; i += NT) {
@@ -1600,7 +1602,8 @@ __device__ void schedule_buckets(const Params &P, uint32_t l, const LvlSeg &g, u
         const unsigned long long pos = uni64(L.pos);
         for (uint32_t b = tid; b < nb; b += NT)
             if (L.kind[b] == 1)
-                seed_task(P, pos + L.rk[b], Task{g.begin + L.bst[b], L.cnt[b], child_depth(sp, h, b), cpar, g.setbase});
+                seed_task(P, pos + L.rk[b],
+                          Task{g.begin + L.bst[b], L.cnt[b], child_depth(sp, h, b0 + b), cpar, g.setbase});
     }
     __syncthreads();
     // small list and chunks
@@ -1642,7 +1645,7 @@ __device__ void schedule_buckets(const Params &P, uint32_t l, const LvlSeg &g, u
     if (db + nsmall > P.desc_cap) return;
     for (uint32_t k = tid; k < nsmall; k += NT) {
         const uint32_t b = L.lsmall[k];
-        P.desc[db + k] = GroupDesc{g.begin + L.bst[b], L.cnt[b], child_depth(sp, h, b), 0u};
+        P.desc[db + k] = GroupDesc{g.begin + L.bst[b], L.cnt[b], child_depth(sp, h, b0 + b), 0u};
     }
     for (uint32_t c = tid; c < nchunk; c += NT) {
         const uint32_t k0 = L.cfirst[c], k1 = L.cfirst[c + 1];
@@ -1672,7 +1675,7 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
     }
     __syncthreads();
     block_scan(L.s.bst, (int)nb, L.s.tmp, true, AddOp(), 0u);
-    schedule_buckets<NBPAD>(P, l, g, nb, L.sp, L.s);
+    schedule_buckets<NBPAD>(P, l, g, 0u, nb, L.sp, L.s);
 }
 
 // ---------------------------------------------------------------------------

@@ -77,8 +77,8 @@ __global__ __launch_bounds__(NT) void k_wsample(Params P) {
         const Rec r = seg_rec(P, g.meta, g.begin + e);
         return kc.key(P.S, r.st, r.ln, hh);
     };
-    select_splitters(L.sp, g.size, g.depth, hash32(g.begin * 0x85EBCA6Bu ^ g.depth * 0xC2B2AE35u ^ g.size), P.wv, 0u,
-                     L.samp, L.srt, L.fl, L.tmp, kload, kc, 1u);
+    select_splitters<8>(L.sp, g.size, g.depth, hash32(g.begin * 0x85EBCA6Bu ^ g.depth * 0xC2B2AE35u ^ g.size), P.wv,
+                        0u, L.samp, L.srt, L.fl, L.tmp, kload, kc, 1u);
     build_jump(L.sp);
     const uint32_t *src = (const uint32_t *)&L.sp;
     uint32_t *dst = (uint32_t *)&P.wsplit[blockIdx.x];
@@ -273,21 +273,29 @@ __global__ __launch_bounds__(NT) void k_wbounds(Params P) {
     }
 }
 
-// Children of a wide segment: bucket sizes and starts from the bounds.
+// Children of a wide segment: bucket sizes and starts from the bounds, one
+// workgroup per NBPAD buckets (their chunks of small buckets stay inside the
+// workgroup's buckets; queue slots and descriptors are reserved per
+// workgroup).
+constexpr uint32_t WSCHED_G = WNBPAD / NBPAD;
 __global__ __launch_bounds__(NT) void k_wschedule(Params P) {
-    __shared__ SchedLDS<WNBPAD> L;
-    if (P.ctl->error || blockIdx.x >= lvl_count(P, 0, 0)) return;
-    const LvlSeg g = P.lseg[0][blockIdx.x];
-    const WSplit &sp = P.wsplit[blockIdx.x];
-    const uint32_t nb = uni(sp.nb);
-    const uint32_t *ws = P.wst + (size_t)blockIdx.x * WNBPAD, *we = P.wen + (size_t)blockIdx.x * WNBPAD;
-    for (uint32_t b = threadIdx.x; b < (uint32_t)WNBPAD; b += NT) {
-        const uint32_t a = ws[b], e = we[b];
-        L.cnt[b] = (b < nb && e > a) ? e - a : 0u;
+    __shared__ SchedLDS<NBPAD> L;
+    const uint32_t seg = blockIdx.x / WSCHED_G, grp = blockIdx.x % WSCHED_G;
+    if (P.ctl->error || seg >= lvl_count(P, 0, 0)) return;
+    const LvlSeg g = P.lseg[0][seg];
+    const WSplit &sp = P.wsplit[seg];
+    const uint32_t nbs = uni(sp.nb);
+    const uint32_t b0 = grp * NBPAD;
+    if (b0 >= nbs) return;
+    const uint32_t nb = min((uint32_t)NBPAD, nbs - b0);
+    const uint32_t *ws = P.wst + (size_t)seg * WNBPAD + b0, *we = P.wen + (size_t)seg * WNBPAD + b0;
+    for (uint32_t b = threadIdx.x; b < (uint32_t)NBPAD; b += NT) {
+        const uint32_t a = b < nb ? ws[b] : 0u, e = b < nb ? we[b] : 0u;
+        L.cnt[b] = e > a ? e - a : 0u;
         L.bst[b] = a;
     }
     __syncthreads();
-    schedule_buckets<WNBPAD>(P, 0, g, nb, sp, L);
+    schedule_buckets<NBPAD>(P, 0, g, b0, nb, sp, L);
 }
 
 // Debug dump of one wide step (the whole input as one segment): keys, the
