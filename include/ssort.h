@@ -260,7 +260,9 @@ const char *ssort_strerror(ssort_status s);
  *            reported as SSORT_EDEVICE by ssort_query_error; they never make
  *            the merge access memory outside its buffers.
  *  lcp_in    device uint32[n]: lcp_in[p] = LCP of the strings at positions
- *            p-1 and p of the same run; the entry at a run's start is ignored
+ *            p-1 and p of the same run; the entry at a run's start is ignored.
+ *            LCPs (in and out) must stay below 2^24 - 8 bytes; a longer one
+ *            is reported as SSORT_EDEVICE
  *  out_perm  device uint32[n]: all indices sorted, equal strings by index
  *  out_lcp   device uint32[n] (may be NULL): out_lcp[0] = 0, out_lcp[i] = LCP
  *            of the strings at positions i-1 and i

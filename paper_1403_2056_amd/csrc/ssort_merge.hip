@@ -25,6 +25,9 @@ using ssd::key_at;
 constexpr int MNT = 64;          // threads per merge workgroup
 constexpr int MKMAX = 32;        // largest K
 constexpr uint32_t SENT = 0xFFFFFFFFu;   // exhausted player
+// A player's LCP and the number of valid characters in its cached word share
+// one 32-bit entry: LCPs up to HMASK - 8 (about 16 MiB) are supported.
+constexpr uint32_t HMASK = 0xFFFFFFu;
 
 struct MergeParams {
     Strs S;
@@ -38,29 +41,46 @@ struct MergeParams {
     uint32_t K, n, g, nsamp;
 };
 
+// Start and length of string id.
+__device__ __forceinline__ void str_ref(const MergeParams &M, uint32_t id, uint64_t *st, uint32_t *ln) {
+    const uint64_t s0 = M.S.off[id];
+    uint64_t l;
+    if (M.S.flags & ssd::TO_END) l = M.S.nchars - s0;
+    else if (M.S.len) l = M.S.len[id];
+    else l = M.S.off[id + 1] - s0;
+    *st = s0;
+    *ln = (uint32_t)l;
+}
+
 __device__ __forceinline__ uint64_t str_key(const MergeParams &M, uint32_t id, uint32_t h) {
-    uint64_t st, ln;
-    st = M.S.off[id];
-    if (M.S.flags & ssd::TO_END) ln = M.S.nchars - st;
-    else if (M.S.len) ln = M.S.len[id];
-    else ln = M.S.off[id + 1] - st;
-    return key_at(M.S.chars, M.S.nchars, st, (uint32_t)ln, h);
+    uint64_t st;
+    uint32_t ln;
+    str_ref(M, id, &st, &ln);
+    return key_at(M.S.chars, M.S.nchars, st, ln, h);
 }
 
 // Compare strings a and b that agree on [0, d): returns their LCP and
-// whether a < b (equal strings: by index).
+// whether a < b (equal strings: by index).  Both strings are located once,
+// then compared 32 characters (four independent 8-byte loads each) a trip.
 __device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, uint32_t b, uint32_t d, bool *a_less) {
-    for (uint32_t l = d;; l += 8) {
-        const uint64_t ka = str_key(M, a, l), kb = str_key(M, b, l);
-        if (ka != kb) {
-            *a_less = ka < kb;
-            return l + (uint32_t)(__clzll(ka ^ kb) >> 3);
-        }
-        if ((ka & 0xFF) == 0) {   // both end here: equal strings
-            *a_less = a < b;
-            uint32_t e = 0;
-            while (e < 8 && ((ka >> (56 - 8 * e)) & 0xFF)) ++e;
-            return l + e;
+    uint64_t sa, sb;
+    uint32_t la, lb;
+    str_ref(M, a, &sa, &la);
+    str_ref(M, b, &sb, &lb);
+    for (uint32_t l = d;; l += 32) {
+        uint64_t ka[4], kb[4];
+        ssd::keys32_at(M.S.chars, M.S.nchars, sa, la, l, ka);
+        ssd::keys32_at(M.S.chars, M.S.nchars, sb, lb, l, kb);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (ka[i] != kb[i]) {
+                *a_less = ka[i] < kb[i];
+                return l + 8 * i + (uint32_t)(__clzll(ka[i] ^ kb[i]) >> 3);
+            }
+            if ((ka[i] & 0xFF) == 0) {   // both end here: equal strings
+                *a_less = a < b;
+                return min(la, lb);
+            }
         }
     }
 }
@@ -73,7 +93,7 @@ __global__ void k_mcache(MergeParams M) {
         for (uint32_t k = 0; k < M.K; ++k) first |= (M.rb[k] == p);
         // every later kernel reads strings through these indices: one outside
         // the set ends the merge with a device error (they check it first)
-        if (M.pin[p] >= M.S.n) {
+        if (M.pin[p] >= M.S.n || (!first && M.hin[p] > HMASK - 8)) {
             atomicOr(M.err, ssd::ERR_MERGE);
             M.cache[p] = 0;
             continue;
@@ -160,16 +180,23 @@ template <int KM>
 struct MergeLDS {
     uint32_t y[KM][MNT];
     uint32_t yi[KM][MNT];   // string id of the loser's current element
-    uint32_t h[KM][MNT];
+    uint32_t h[KM][MNT];    // its LCP with the game's winner | valid cached characters << 24
     uint64_t c[KM][MNT];
     uint32_t pos[KM][MNT];   // next element of each run (absolute)
     uint32_t end[KM][MNT];
 };
 
+__device__ __forceinline__ uint32_t hv_pack(uint32_t h, uint32_t v) { return h | (v << 24); }
+
 // One game (Algorithm 2 with cached characters): the candidate (x, hx, cx)
 // against the node's loser (y, hy, cy), both with LCPs against the same
-// smaller string p.  Returns true when the candidate wins; the loser's
-// (run, LCP with the winner, characters at it) end up in (ly, lh, lc).
+// smaller string p; hx and hy carry, above their LCP, how many of the cached
+// characters (the word's leading bytes, taken at the LCP) are valid.  Returns
+// true when the candidate wins; the loser's LCP with the winner (and its valid
+// count) and its characters at that LCP end up in (lh, lc).  When the cached
+// characters decide, the loser's word is shifted to its new LCP and keeps the
+// rest of its valid characters, so the strings themselves are read only when
+// every valid cached character is equal.
 __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t xid, uint32_t hx, uint64_t cx,
                                      uint32_t y, uint32_t yid, uint32_t hy, uint64_t cy, uint32_t *lh, uint64_t *lc) {
     if (y == SENT) {
@@ -182,34 +209,50 @@ __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t 
         *lc = cx;
         return false;
     }
-    if (hx > hy) {   // the candidate agrees longer with p: it is smaller
+    const uint32_t lx = hx & HMASK, ly = hy & HMASK;
+    if (lx > ly) {   // the candidate agrees longer with p: it is smaller
         *lh = hy;
         *lc = cy;
         return true;
     }
-    if (hx < hy) {
+    if (lx < ly) {
         *lh = hx;
         *lc = cx;
         return false;
     }
-    // equal LCPs: compare characters from there, the cached 8 first
-    uint32_t l;
+    // equal LCPs: compare characters from there, the valid cached ones first
+    const uint32_t m = min(hx >> 24, hy >> 24);   // characters valid in both words
+    const uint64_t vm = m >= 8 ? ~0ull : ~(~0ull >> (8 * m));
+    const uint64_t z = (cx ^ cy) & vm;
     bool x_less;
-    if (cx != cy) {
-        x_less = cx < cy;
-        l = hx + (uint32_t)(__clzll(cx ^ cy) >> 3);
-    } else if ((cx & 0xFF) == 0) {
-        x_less = xid < yid;
-        uint32_t e = 0;
-        while (e < 8 && ((cx >> (56 - 8 * e)) & 0xFF)) ++e;
-        l = hx + e;
+    uint32_t e;   // equal characters from the LCP on
+    if (z) {
+        x_less = (cx & vm) < (cy & vm);
+        e = (uint32_t)(__clzll(z) >> 3);
     } else {
-        l = cmp_from(M, xid, yid, hx + 8, &x_less);
+        // an end of string among the equal valid characters: identical strings
+        uint32_t t = 0;
+        while (t < m && ((cx >> (56 - 8 * t)) & 0xFF)) ++t;
+        if (t < m) {
+            x_less = xid < yid;
+            e = t;
+        } else {
+            uint32_t l = cmp_from(M, xid, yid, lx + m, &x_less);
+            if (l > HMASK - 8) {   // beyond the packed LCP range: a device error, never a wrong order
+                atomicOr(M.err, ssd::ERR_MERGE);
+                l = HMASK - 8;
+            }
+            const uint32_t lid = x_less ? yid : xid;
+            *lh = hv_pack(l, 8);
+            *lc = str_key(M, lid, l);
+            return x_less;
+        }
     }
-    const uint32_t lid = x_less ? yid : xid;
+    // the loser keeps its characters after the first e
     const uint64_t lold = x_less ? cy : cx;
-    *lh = l;
-    *lc = (l == hx) ? lold : str_key(M, lid, l);
+    const uint32_t vold = (x_less ? hy : hx) >> 24;
+    *lh = hv_pack(lx + e, vold - e);
+    *lc = e ? lold << (8 * e) : lold;
     return x_less;
 }
 
@@ -268,7 +311,7 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         uint32_t id;
         if (player(r, &id)) {
             wrun[r] = r;
-            wh[r] = 0;
+            wh[r] = hv_pack(0, 8);
             wc[r] = str_key(M, id, 0);
         } else {
             wrun[r] = SENT;
@@ -301,11 +344,12 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         }
     }
     uint32_t w = wrun[0], hw = 0;
+    uint32_t wid = w != SENT ? M.pin[L.pos[w][me]] : 0u;
     bool first = true;
     while (w != SENT) {
         const uint32_t p = L.pos[w][me];
-        M.pout[out] = M.pin[p];
-        if (!first && M.hout) M.hout[out] = hw;
+        M.pout[out] = wid;
+        if (!first && M.hout) M.hout[out] = hw & HMASK;
         first = false;
         ++out;
         // the winner's run advances; its next element's LCP with the string
@@ -315,7 +359,7 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         uint64_t cx = 0;
         uint32_t xid = 0;
         if (p + 1 < L.end[w][me]) {
-            hx = M.hin[p + 1];
+            hx = hv_pack(M.hin[p + 1], 8);
             cx = M.cache[p + 1];
             xid = M.pin[p + 1];
         } else {
@@ -341,6 +385,7 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             L.c[v][me] = lc;
         }
         w = x;
+        wid = xid;
         hw = hx;
     }
 }
