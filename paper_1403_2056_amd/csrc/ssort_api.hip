@@ -564,6 +564,7 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
     M.hout = out_lcp;
     char *w = (char *)ws;
     M.err = &((Ctl *)(w + L.ctl))->error;
+    M.next_job = &((Ctl *)(w + L.ctl))->head;
     M.cache = (uint64_t *)(w + L.cache);
     M.cuts = (uint32_t *)(w + L.cuts);
     M.K = K;

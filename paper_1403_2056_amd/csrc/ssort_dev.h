@@ -63,11 +63,14 @@ __device__ __forceinline__ uint64_t key_at(const uint8_t *chars, uint64_t nchars
     const uint64_t p = st + h;
     if (p >= nchars) return 0;   // never read outside the buffer (valid inputs never get here)
     const uint32_t rem = (uint32_t)min((uint64_t)(ln - h), nchars - p);
-    const uintptr_t a = (uintptr_t)(chars + p);
-    const uintptr_t a0 = a & ~(uintptr_t)7;
-    const uint32_t sh = (uint32_t)(a & 7);
-    uint64_t w = *(const uint64_t *)a0 >> (8 * sh);
-    if (sh != 0 && rem > 8 - sh) w |= *(const uint64_t *)(a0 + 8) << (64 - 8 * sh);
+    // the aligned words by pointer arithmetic from `chars` (not through an
+    // integer), so that the loads stay global-memory loads: a generic (flat)
+    // load would also count against the LDS wait counter and every later LDS
+    // wait would wait for it
+    const uint32_t sh = (uint32_t)((uintptr_t)(chars + p) & 7);
+    const uint64_t *a0 = reinterpret_cast<const uint64_t *>(chars + (p - sh));
+    uint64_t w = a0[0] >> (8 * sh);
+    if (sh != 0 && rem > 8 - sh) w |= a0[1] << (64 - 8 * sh);
     uint64_t k = __builtin_bswap64(w);
     if (rem < 8) k &= ~0ull << (8 * (8 - rem));
     return k;
@@ -109,13 +112,12 @@ struct PackedKey {
         const uint64_t p = st + h;
         if (p >= S.nchars) return 0;
         const uint32_t r = (uint32_t)min((uint64_t)min(ln - h, nq), S.nchars - p);
-        const uintptr_t a = (uintptr_t)(S.chars + p);
-        const uintptr_t a0 = a & ~(uintptr_t)7;
-        const uint32_t sh = (uint32_t)(a & 7);
+        const uint32_t sh = (uint32_t)((uintptr_t)(S.chars + p) & 7);
+        const uint64_t *a0 = reinterpret_cast<const uint64_t *>(S.chars + (p - sh));
         const uint32_t nw = (sh + r + 7) >> 3;   // aligned words holding the r characters, 1..5
         uint64_t w[5];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) w[i] = (uint32_t)i < nw ? *(const uint64_t *)(a0 + 8 * i) : 0ull;
+        for (int i = 0; i < 5; ++i) w[i] = (uint32_t)i < nw ? a0[i] : 0ull;
         // u0..u3: characters p + 8i .. p + 8i + 7 in little-endian byte order
         const uint64_t u0 = sh ? (w[0] >> (8 * sh)) | (w[1] << (64 - 8 * sh)) : w[0];
         const uint64_t u1 = sh ? (w[1] >> (8 * sh)) | (w[2] << (64 - 8 * sh)) : w[1];
@@ -155,13 +157,12 @@ __device__ __forceinline__ void keys32_at(const uint8_t *chars, uint64_t nchars,
     const uint64_t p = st + h;
     if (p >= nchars) return;
     const uint32_t rem = (uint32_t)min((uint64_t)(ln - h), nchars - p);
-    const uintptr_t a = (uintptr_t)(chars + p);
-    const uintptr_t a0 = a & ~(uintptr_t)7;
-    const uint32_t sh = (uint32_t)(a & 7);
+    const uint32_t sh = (uint32_t)((uintptr_t)(chars + p) & 7);
+    const uint64_t *a0 = reinterpret_cast<const uint64_t *>(chars + (p - sh));
     const uint32_t nw = (sh + min(rem, 32u) + 7) >> 3;   // words holding wanted bytes, 1..5
     uint64_t w[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) w[i] = (uint32_t)i < nw ? *(const uint64_t *)(a0 + 8 * i) : 0ull;
+    for (int i = 0; i < 5; ++i) w[i] = (uint32_t)i < nw ? a0[i] : 0ull;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint64_t lo = sh ? (w[j] >> (8 * sh)) | (w[j + 1] << (64 - 8 * sh)) : w[j];

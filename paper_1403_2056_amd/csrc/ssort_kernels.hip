@@ -189,15 +189,21 @@ __device__ __forceinline__ void scatter_chunk(ScatterLDS<K, PAY> &L, uint32_t *t
     __syncthreads();
 }
 
+// A running minimum kept in LDS and lowered by other lanes, read afresh: an
+// LDS load (through a generic pointer it would be a flat load, which also
+// waits behind every global load in flight).
+typedef uint32_t __attribute__((address_space(3))) lds_u32;
+__device__ __forceinline__ uint32_t ld_stop(const uint32_t *p) { return *(volatile const lds_u32 *)p; }
+
 // Length of the common prefix of strings a and b, known to agree on [0, from),
 // compared 32 bytes (four independent 8-byte loads per string) at a time and
 // given up once it reaches `stop` (the caller only needs values below it).
 // Equal words that end both strings mean the strings are identical.
 __device__ __forceinline__ uint32_t lcp_from(const Params &P, uint64_t sta, uint32_t lna, uint64_t stb, uint32_t lnb,
-                                             uint32_t from, const volatile uint32_t *stop) {
+                                             uint32_t from, const uint32_t *stop) {
     uint32_t l = from;
     for (;;) {
-        if (l >= *stop) return l;
+        if (l >= ld_stop(stop)) return l;
         uint64_t ka[4], kb[4];
         keys32_at(P.S.chars, P.S.nchars, sta, lna, l, ka);
         keys32_at(P.S.chars, P.S.nchars, stb, lnb, l, kb);
@@ -232,7 +238,7 @@ __device__ __forceinline__ uint32_t group_width(uint32_t n) {
 // 64 lanes of the wave together (groups with on == false take part without a
 // pair); the wave loops until its last group is done.
 __device__ __forceinline__ uint32_t group_lcp(const Params &P, uint32_t G, bool on, uint64_t sta, uint32_t lna,
-                                              uint64_t stb, uint32_t lnb, uint32_t from, const volatile uint32_t *stop) {
+                                              uint64_t stb, uint32_t lnb, uint32_t from, const uint32_t *stop) {
     const uint32_t lane = lane_id();
     const uint32_t gl = lane & (G - 1), gb = lane & ~(G - 1);
     const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << G) - 1) << gb;
@@ -243,7 +249,7 @@ __device__ __forceinline__ uint32_t group_lcp(const Params &P, uint32_t G, bool 
         uint32_t v = 0;
         if (live) {
             const uint32_t pos = l + 8 * gl;
-            const bool cut = pos >= *stop;
+            const bool cut = pos >= ld_stop(stop);
             uint64_t ka = 0, kb = 0;
             if (!cut) {
                 ka = key_at(P.S.chars, P.S.nchars, sta, lna, pos);
@@ -1175,24 +1181,26 @@ __global__ __launch_bounds__(NT) void k_alpha_scan(Params P) {
     if (threadIdx.x < 8) bm[threadIdx.x] = 0;
     __syncthreads();
     const uintptr_t a = (uintptr_t)P.S.chars, e = a + P.S.nchars;
-    const uintptr_t a0 = a & ~(uintptr_t)7;
-    const uint64_t nw = P.S.nchars ? (e + 7 - a0) >> 3 : 0;
+    const uint32_t lead = (uint32_t)(a & 7);   // bytes of the first aligned word before the buffer
+    const uint64_t nw = P.S.nchars ? (e + 7 - (a - lead)) >> 3 : 0;
     uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)NT + threadIdx.x; i < nw; i += (uint64_t)gridDim.x * NT) {
-        const uintptr_t wa = a0 + 8 * i;
-        const bool whole = wa >= a && wa + 8 <= e;
+        // word i starts lead bytes before chars + 8i (pointer arithmetic from
+        // chars: the loads stay global-memory loads)
+        const int64_t o = (int64_t)(8 * i) - (int64_t)lead;   // its offset from chars
+        const bool whole = o >= 0 && (uint64_t)o + 8 <= P.S.nchars;
         // the two edge words are read byte by byte: no load leaves the buffer
         uint64_t w = 0;
         if (whole) {
-            w = *(const uint64_t *)wa;
+            w = *reinterpret_cast<const uint64_t *>(P.S.chars + o);
         } else {
             for (int b = 0; b < 8; ++b)
-                if (wa + b >= a && wa + b < e) w |= (uint64_t)*(const uint8_t *)(wa + b) << (8 * b);
+                if (o + b >= 0 && (uint64_t)(o + b) < P.S.nchars) w |= (uint64_t)P.S.chars[o + b] << (8 * b);
         }
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const uint32_t c = (uint32_t)(w >> (8 * b)) & 0xFF;
-            const bool in = whole || (wa + b >= a && wa + b < e);
+            const bool in = whole || (o + b >= 0 && (uint64_t)(o + b) < P.S.nchars);
             const uint64_t bit = in ? 1ull << (c & 63) : 0ull;
             m0 |= (c >> 6) == 0 ? bit : 0ull;
             m1 |= (c >> 6) == 1 ? bit : 0ull;

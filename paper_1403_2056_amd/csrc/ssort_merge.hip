@@ -25,6 +25,7 @@ using ssd::key_at;
 constexpr int MNT = 64;          // threads per merge workgroup
 constexpr int MKMAX = 32;        // largest K
 constexpr uint32_t SENT = 0xFFFFFFFFu;   // exhausted player
+constexpr uint32_t WAITING = 0xFFFFFFFEu;   // tree build: no player has reached the node yet
 // A player's LCP and the number of valid characters in its cached word share
 // one 32-bit entry: LCPs up to HMASK - 8 (about 16 MiB) are supported.
 constexpr uint32_t HMASK = 0xFFFFFFu;
@@ -38,6 +39,7 @@ struct MergeParams {
     uint64_t *cache;         // 8 characters of each input string at its LCP
     uint32_t *cuts;          // (nsamp + 1) rows of K cuts, in sample order
     unsigned long long *err;
+    unsigned long long *next_job;   // next merge job to claim
     uint32_t K, n, g, nsamp;
 };
 
@@ -259,8 +261,7 @@ __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t 
 template <int KM>
 __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     __shared__ MergeLDS<KM> L;
-    const uint32_t j = blockIdx.x * MNT + threadIdx.x;
-    if (j >= M.nsamp || *M.err) return;
+    if (*M.err) return;
     const int me = threadIdx.x;
     const uint32_t K = M.K;
     uint32_t KP = 1;
@@ -269,6 +270,13 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         atomicOr(M.err, ssd::ERR_MERGE);
         return;
     }
+    // Jobs are claimed one at a time from a shared counter: their lengths
+    // vary (about exponentially around g), and a wave that held one job per
+    // lane would run as long as its longest job.
+    for (;;) {
+    const uint32_t j = (uint32_t)min(__hip_atomic_fetch_add(M.next_job, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                     (unsigned long long)M.nsamp);
+    if (j >= M.nsamp || *M.err) return;
     // this job: for each run, the elements between cut rows j and j+1; a
     // row the sample search left unwritten (two samples of the same rank:
     // runs that are not sorted by (string, index), or an index in two runs)
@@ -296,55 +304,62 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         return;
     }
     // players: the runs' first elements of the job, LCP 0 against the empty
-    // string; the tree is built bottom-up with the winners of subtrees kept
-    // in the leaf slots' place (node v < KP holds a loser, win[] the winner)
-    uint32_t wrun[KM];
-    uint32_t wh[KM];
-    uint64_t wc[KM];
-    auto player = [&](uint32_t r, uint32_t *id) -> bool {
-        if (r >= K || L.pos[r][me] >= L.end[r][me]) return false;
-        *id = M.pin[L.pos[r][me]];
-        return true;
-    };
-    // leaves
+    // string.  The tree is built by inserting them one after the other: a
+    // player climbs from its leaf, stops at the first node no player of the
+    // other subtree has reached yet (it waits there), and otherwise plays
+    // the waiting player, the loser staying at the node with its LCP against
+    // the winner.  Inserted left to right, each subtree is complete when its
+    // last player arrives, so every game is between the winners of two
+    // subtrees, both with LCPs against the empty string; the player that
+    // passes the root is the first winner.  Only the node arrays in LDS and
+    // the climbing player's registers are used.
+    for (uint32_t v = 1; v < KP; ++v) L.y[v][me] = WAITING;
+    uint32_t w = SENT, hw = 0, wid = 0;
     for (uint32_t r = 0; r < KP; ++r) {
-        uint32_t id;
-        if (player(r, &id)) {
-            wrun[r] = r;
-            wh[r] = hv_pack(0, 8);
-            wc[r] = str_key(M, id, 0);
-        } else {
-            wrun[r] = SENT;
-            wh[r] = 0;
-            wc[r] = 0;
+        uint32_t x = SENT, xid = 0, hx = 0;
+        uint64_t cx = 0;
+        if (r < K && L.pos[r][me] < L.end[r][me]) {
+            x = r;
+            xid = M.pin[L.pos[r][me]];
+            hx = hv_pack(0, 8);
+            cx = str_key(M, xid, 0);
         }
-    }
-    // internal nodes, level by level: the winners of nodes at one level are
-    // compacted into wrun[0..cnt)
-    for (uint32_t cnt = KP, base = KP; cnt > 1; cnt >>= 1, base >>= 1) {
-        for (uint32_t q = 0; q < cnt / 2; ++q) {
-            const uint32_t a = wrun[2 * q], b = wrun[2 * q + 1];
-            uint32_t aid = 0, bid = 0;
-            if (a != SENT) aid = M.pin[L.pos[a][me]];
-            if (b != SENT) bid = M.pin[L.pos[b][me]];
+        bool waits = false;
+        for (uint32_t v = (KP + r) >> 1; v >= 1; v >>= 1) {
+            const uint32_t y = L.y[v][me];
+            if (y == WAITING) {
+                L.y[v][me] = x;
+                L.yi[v][me] = xid;
+                L.h[v][me] = hx;
+                L.c[v][me] = cx;
+                waits = true;
+                break;
+            }
+            const uint32_t yid = L.yi[v][me];
+            const uint32_t hy = L.h[v][me];
+            const uint64_t cy = L.c[v][me];
             uint32_t lh;
             uint64_t lc;
-            const bool aw = game(M, a, aid, wh[2 * q], wc[2 * q], b, bid, wh[2 * q + 1], wc[2 * q + 1], &lh, &lc);
-            const uint32_t v = (base >> 1) + q;   // node index of this game
-            L.y[v][me] = aw ? b : a;
-            L.yi[v][me] = aw ? bid : aid;
+            if (game(M, x, xid, hx, cx, y, yid, hy, cy, &lh, &lc)) {
+                L.y[v][me] = y;
+                L.yi[v][me] = yid;
+            } else {
+                L.y[v][me] = x;
+                L.yi[v][me] = xid;
+                x = y;
+                xid = yid;
+                hx = hy;
+                cx = cy;
+            }
             L.h[v][me] = lh;
             L.c[v][me] = lc;
-            const uint32_t wr = aw ? a : b;
-            const uint32_t whh = aw ? wh[2 * q] : wh[2 * q + 1];
-            const uint64_t wcc = aw ? wc[2 * q] : wc[2 * q + 1];
-            wrun[q] = wr;
-            wh[q] = whh;
-            wc[q] = wcc;
+        }
+        if (!waits) {
+            w = x;
+            wid = xid;
+            hw = hx;
         }
     }
-    uint32_t w = wrun[0], hw = 0;
-    uint32_t wid = w != SENT ? M.pin[L.pos[w][me]] : 0u;
     bool first = true;
     while (w != SENT) {
         const uint32_t p = L.pos[w][me];
@@ -388,6 +403,7 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         wid = xid;
         hw = hx;
     }
+    }
 }
 
 // LCP between the first output of each job and the string before it (after
@@ -417,7 +433,10 @@ __global__ void k_mreset(MergeParams M) {
     const size_t total = (size_t)(M.nsamp + 1) * M.K;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
         M.cuts[i] = SENT;
-    if (threadIdx.x == 0 && blockIdx.x == 0) *M.err = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *M.err = 0;
+        *M.next_job = 0;
+    }
 }
 
 }  // namespace ssm

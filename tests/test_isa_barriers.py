@@ -104,3 +104,27 @@ def test_release_check_detects_a_missing_wait():
     assert _waited_before_barrier(body) == [1]
     body.insert(2, "\ts_waitcnt vmcnt(0) expcnt(0) lgkmcnt(0)")
     assert _waited_before_barrier(body) == []
+
+
+def test_no_flat_memory_access(asm):
+    """Every load and store names its address space: a flat (generic) access
+    also counts against the LDS wait counter, so each later LDS wait would
+    wait for the global loads in flight (character gathers issued as flat
+    loads serialised the kernels that interleave them with LDS work)."""
+    lines = asm.read_text().splitlines()
+    bad = {}
+    for k, body in isa_barriers.kernels(lines):
+        n = sum(1 for ln in body if ln.strip().startswith(("flat_load", "flat_store", "flat_atomic")))
+        if n:
+            bad[k] = n
+    assert not bad, bad
+
+
+def test_merge_without_scratch(asm):
+    """The K-way merge's per-lane loser-tree build keeps its winners in
+    registers (statically indexed), not in scratch memory."""
+    text = asm.read_text()
+    blocks = re.findall(r"\.name:\s+(\S+)\n(?:.*\n){0,40}?\s+\.private_segment_fixed_size:\s+(\d+)", text)
+    merges = {n: int(sz) for n, sz in blocks if "k_mmerge" in n}
+    assert len(merges) == 5, merges
+    assert all(sz == 0 for sz in merges.values()), merges
