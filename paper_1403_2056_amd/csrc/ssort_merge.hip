@@ -62,9 +62,12 @@ __device__ __forceinline__ uint64_t str_key(const MergeParams &M, uint32_t id, u
 }
 
 // Compare strings a and b that agree on [0, d): returns their LCP and
-// whether a < b (equal strings: by index).  Both strings are located once,
-// then compared 32 characters (four independent 8-byte loads each) a trip.
-__device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, uint32_t b, uint32_t d, bool *a_less) {
+// whether a < b (equal strings: by index), and in *lw the loser's characters
+// at the LCP (the word's leading *lv of them valid), taken from the bytes
+// just compared.  Both strings are located once, then compared 32 characters
+// (four independent 8-byte loads each) a trip.
+__device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, uint32_t b, uint32_t d, bool *a_less,
+                                             uint64_t *lw, uint32_t *lv) {
     uint64_t sa, sb;
     uint32_t la, lb;
     str_ref(M, a, &sa, &la);
@@ -73,18 +76,39 @@ __device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, u
         uint64_t ka[4], kb[4];
         ssd::keys32_at(M.S.chars, M.S.nchars, sa, la, l, ka);
         ssd::keys32_at(M.S.chars, M.S.nchars, sb, lb, l, kb);
+        // the first word that differs or ends both strings (selects only:
+        // no indexing of the word arrays by a computed index)
+        uint32_t i = 4;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (ka[i] != kb[i]) {
-                *a_less = ka[i] < kb[i];
-                return l + 8 * i + (uint32_t)(__clzll(ka[i] ^ kb[i]) >> 3);
-            }
-            if ((ka[i] & 0xFF) == 0) {   // both end here: equal strings
-                *a_less = a < b;
-                return min(la, lb);
-            }
+        for (int t = 3; t >= 0; --t)
+            if (ka[t] != kb[t] || (ka[t] & 0xFF) == 0) i = (uint32_t)t;
+        if (i == 4) continue;
+        auto pick = [](const uint64_t *k, uint32_t j) -> uint64_t {
+            return j == 0 ? k[0] : j == 1 ? k[1] : j == 2 ? k[2] : j == 3 ? k[3] : 0ull;
+        };
+        const uint64_t xa = pick(ka, i), xb = pick(kb, i);
+        if (xa == xb) {   // both end in this word: equal strings
+            *a_less = a < b;
+            *lw = 0;   // past the end
+            *lv = 8;
+            return min(la, lb);
         }
+        const bool al = xa < xb;
+        *a_less = al;
+        const uint32_t e = (uint32_t)(__clzll(xa ^ xb) >> 3);
+        // the loser's 8 characters from the difference on
+        const uint64_t w0 = al ? xb : xa;
+        const uint64_t w1 = al ? pick(kb, i + 1) : pick(ka, i + 1);
+        *lw = e ? (w0 << (8 * e)) | (w1 >> (64 - 8 * e)) : w0;
+        *lv = (i + 1 < 4 || e == 0) ? 8u : 8u - e;
+        return l + 8 * i + e;
     }
+}
+
+__device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, uint32_t b, uint32_t d, bool *a_less) {
+    uint64_t w;
+    uint32_t v;
+    return cmp_from(M, a, b, d, a_less, &w, &v);
 }
 
 // 8 characters at the LCP position of every input element (the run's first
@@ -239,14 +263,15 @@ __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t 
             x_less = xid < yid;
             e = t;
         } else {
-            uint32_t l = cmp_from(M, xid, yid, lx + m, &x_less);
+            uint64_t lw;
+            uint32_t lv;
+            uint32_t l = cmp_from(M, xid, yid, lx + m, &x_less, &lw, &lv);
             if (l > HMASK - 8) {   // beyond the packed LCP range: a device error, never a wrong order
                 atomicOr(M.err, ssd::ERR_MERGE);
                 l = HMASK - 8;
             }
-            const uint32_t lid = x_less ? yid : xid;
-            *lh = hv_pack(l, 8);
-            *lc = str_key(M, lid, l);
+            *lh = hv_pack(l, lv);
+            *lc = lw;
             return x_less;
         }
     }
