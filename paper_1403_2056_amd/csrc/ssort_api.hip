@@ -210,8 +210,9 @@ void launch_alphabet(const ssort_ctx *c, const Params &P, hipStream_t s) {
 }
 
 void launch_seam(const ssort_ctx *c, const Params &P, hipStream_t s) {
-    if (packed(c)) hipLaunchKernelGGL((k_seam<true>), dim3(grid_for(P.S.n)), dim3(NT), 0, s, P);
-    else hipLaunchKernelGGL((k_seam<false>), dim3(grid_for(P.S.n)), dim3(NT), 0, s, P);
+    const dim3 g((uint32_t)(((uint64_t)P.S.n + SEAM_RANGE - 1) / SEAM_RANGE));
+    if (packed(c)) hipLaunchKernelGGL((k_seam<true>), g, dim3(NT), 0, s, P);
+    else hipLaunchKernelGGL((k_seam<false>), g, dim3(NT), 0, s, P);
 }
 
 // The whole-GPU levels (grids sized for each level's capacity; workgroups

@@ -1696,62 +1696,84 @@ __global__ __launch_bounds__(NT) void k_lvl_schedule(Params P, uint32_t l) {
 // unwritten (the outputs are undefined then), so the pass does not run: an
 // unwritten entry is not a string index.  An index outside a set is a device
 // error too, never an access.
+// Each workgroup takes SEAM_RANGE consecutive positions, SU per thread, each
+// stage's loads issued for all of them before the next stage needs the
+// results (the lcp word, the two permutation entries, the two records, the
+// two keys), so the dependent round trips overlap across positions.  In a
+// batched sort the permutation is set-local: the boundaries of the sets that
+// overlap the range are staged in LDS once (one search in device memory per
+// workgroup), and each seam finds its set there.
+constexpr int SU = 4;
+constexpr uint32_t SEAM_RANGE = NT * SU;
 template <bool Z>
-__global__ void k_seam(Params P) {
+__global__ __launch_bounds__(NT) void k_seam(Params P) {
+    __shared__ uint32_t sb[SEAM_RANGE + 2];
+    __shared__ uint32_t sfirst;
     if (P.ctl->error) return;
     const uint32_t n = P.S.n;
+    const uint32_t r0 = blockIdx.x * SEAM_RANGE;
+    if (r0 >= n) return;
     const auto kc = KeyOf<Z>::make(P);
-    // SU positions per thread and trip, each stage's loads issued for all of
-    // them before the next stage needs the results (the lcp word, the two
-    // permutation entries, the two records, the two keys), so the dependent
-    // round trips overlap across positions instead of adding up
-    constexpr int SU = 4;
-    const uint32_t stride = gridDim.x * NT;
-    for (uint32_t p0 = blockIdx.x * NT + threadIdx.x + 1; p0 < n; p0 += SU * stride) {
-        uint32_t v[SU], ia[SU], ib[SU];
-        bool on[SU];
-#pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const uint32_t p = p0 + u * stride;
-            v[u] = p < n ? P.lcp[p] : 0u;
-            on[u] = (v[u] & SEAM) != 0;
-        }
-#pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            ia[u] = 0;
-            ib[u] = 0;
-            if (!on[u]) continue;
-            const uint32_t p = p0 + u * stride;
-            uint32_t base = 0;
-            if (P.set_begin) {
-                uint32_t lo = 0, hi = P.m;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (P.set_begin[mid] <= p) lo = mid; else hi = mid;
-                }
-                base = P.set_begin[lo];
+    if (P.set_begin) {
+        if (threadIdx.x == 0) {
+            uint32_t lo = 0, hi = P.m;   // last set starting at or before r0
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (P.set_begin[mid] <= r0) lo = mid; else hi = mid;
             }
-            ia[u] = P.perm[p - 1] + base;
-            ib[u] = P.perm[p] + base;
-            if (ia[u] >= n || ib[u] >= n) {
-                atomicOr(&P.ctl->error, ERR_SEAM);
-                on[u] = false;
+            sfirst = lo;
+        }
+        __syncthreads();
+        // the boundaries from that set on; past the last set, above every position
+        for (uint32_t i = threadIdx.x; i < SEAM_RANGE + 2; i += NT) {
+            const uint32_t j = sfirst + i;
+            sb[i] = j < P.m ? P.set_begin[j] : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+    }
+    uint32_t v[SU], ia[SU], ib[SU];
+    bool on[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const uint32_t p = r0 + threadIdx.x + u * NT;
+        v[u] = (p >= 1 && p < n) ? P.lcp[p] : 0u;
+        on[u] = (v[u] & SEAM) != 0;
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        ia[u] = 0;
+        ib[u] = 0;
+        if (!on[u]) continue;
+        const uint32_t p = r0 + threadIdx.x + u * NT;
+        uint32_t base = 0;
+        if (P.set_begin) {
+            uint32_t lo = 0, hi = SEAM_RANGE + 2;   // last boundary at or before p (sb[0] <= r0 <= p)
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (sb[mid] <= p) lo = mid; else hi = mid;
             }
+            base = sb[lo];
         }
-        Rec ra[SU], rb[SU];
+        ia[u] = P.perm[p - 1] + base;
+        ib[u] = P.perm[p] + base;
+        if (ia[u] >= n || ib[u] >= n) {
+            atomicOr(&P.ctl->error, ERR_SEAM);
+            on[u] = false;
+        }
+    }
+    Rec ra[SU], rb[SU];
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            if (!on[u]) continue;
-            ra[u] = make_rec(P.S, ia[u]);
-            rb[u] = make_rec(P.S, ib[u]);
-        }
+    for (int u = 0; u < SU; ++u) {
+        if (!on[u]) continue;
+        ra[u] = make_rec(P.S, ia[u]);
+        rb[u] = make_rec(P.S, ib[u]);
+    }
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            if (!on[u]) continue;
-            const uint32_t h = v[u] & ~SEAM;
-            const uint64_t z = kc.key(P.S, ra[u].st, ra[u].ln, h) ^ kc.key(P.S, rb[u].st, rb[u].ln, h);
-            P.lcp[p0 + u * stride] = h + (z ? kc.eqc(z) : kc.q());
-        }
+    for (int u = 0; u < SU; ++u) {
+        if (!on[u]) continue;
+        const uint32_t h = v[u] & ~SEAM;
+        const uint64_t z = kc.key(P.S, ra[u].st, ra[u].ln, h) ^ kc.key(P.S, rb[u].st, rb[u].ln, h);
+        P.lcp[r0 + threadIdx.x + u * NT] = h + (z ? kc.eqc(z) : kc.q());
     }
 }
 
