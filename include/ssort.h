@@ -267,8 +267,8 @@ const char *ssort_strerror(ssort_status s);
  *  out_lcp   device uint32[n] (may be NULL): out_lcp[0] = 0, out_lcp[i] = LCP
  *            of the strings at positions i-1 and i
  * When the runs together hold every index of `in` once, the result equals
- * ssort_sort of `in`.  Workspace from ssort_merge_workspace_bytes (a few bytes
- * per string).  Asynchronous on `stream`; ssort_query_error reports device
+ * ssort_sort of `in`.  Workspace from ssort_merge_workspace_bytes (about 40
+ * bytes per string).  Asynchronous on `stream`; ssort_query_error reports device
  * errors.  SSORT_EINVAL for bad runs or K. */
 ssort_status ssort_merge_workspace_bytes(const ssort_ctx *ctx, const uint32_t *run_begin, uint32_t K, size_t *bytes);
 ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t *run_begin, uint32_t K,

@@ -501,10 +501,11 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
 // ---- K-way LCP-merge ----
 namespace {
 constexpr uint32_t MERGE_G = 128;   // sample spacing: n / MERGE_G jobs of about MERGE_G strings each
+constexpr uint32_t MERGE_LCAP = 128;   // longer jobs are split
 
 struct MergeLayout {
-    size_t ctl, cache, cuts, total;
-    uint32_t nsamp;
+    size_t ctl, ent, cuts, ja, jb, total;
+    uint32_t nsamp, xcap;
 };
 
 MergeLayout merge_layout(uint32_t n, const uint32_t *run_begin, uint32_t K) {
@@ -514,10 +515,15 @@ MergeLayout merge_layout(uint32_t n, const uint32_t *run_begin, uint32_t K) {
     size_t off = 0;
     L.ctl = off;
     off = align_up(off + sizeof(Ctl), 256);
-    L.cache = off;
-    off = align_up(off + 8 * (size_t)n, 256);
+    L.ent = off;
+    off = align_up(off + sizeof(ssm::MEnt) * (size_t)n, 256);
+    L.xcap = n / MERGE_LCAP + 1;
     L.cuts = off;
-    off = align_up(off + 4 * (size_t)(L.nsamp + 1) * K, 256);
+    off = align_up(off + 4 * (size_t)(L.nsamp + 1 + L.xcap) * K, 256);
+    L.ja = off;
+    off = align_up(off + 4 * (size_t)(L.nsamp + L.xcap), 256);
+    L.jb = off;
+    off = align_up(off + 4 * (size_t)(L.nsamp + L.xcap), 256);
     L.total = off;
     return L;
 }
@@ -566,12 +572,17 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
     char *w = (char *)ws;
     M.err = &((Ctl *)(w + L.ctl))->error;
     M.next_job = &((Ctl *)(w + L.ctl))->head;
-    M.cache = (uint64_t *)(w + L.cache);
+    M.nsplit = &((Ctl *)(w + L.ctl))->tail;
+    M.ent = (ssm::MEnt *)(w + L.ent);
     M.cuts = (uint32_t *)(w + L.cuts);
+    M.ja = (uint32_t *)(w + L.ja);
+    M.jb = (uint32_t *)(w + L.jb);
     M.K = K;
     M.n = n;
     M.g = MERGE_G;
     M.nsamp = L.nsamp;
+    M.lcap = MERGE_LCAP;
+    M.xcap = L.xcap;
     hipLaunchKernelGGL(ssm::k_mreset, dim3(grid_for((uint64_t)(L.nsamp + 1) * K)), dim3(NT), 0, s, M);
     hipLaunchKernelGGL(ssm::k_mcache, dim3(grid_for(n)), dim3(NT), 0, s, M);
     {
@@ -579,6 +590,7 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
         uint32_t kps = 1;
         while (kps < K) kps <<= 1;
         hipLaunchKernelGGL(ssm::k_msample, dim3((uint32_t)(((size_t)L.nsamp * kps + 63) / 64)), dim3(64), 0, s, M);
+        hipLaunchKernelGGL(ssm::k_msplit, dim3((uint32_t)(((size_t)L.nsamp * kps + 63) / 64)), dim3(64), 0, s, M);
     }
     {
         // the loser tree's LDS arrays sized for the smallest power of two >= K
@@ -591,7 +603,7 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
         else if (kp == 16) hipLaunchKernelGGL(ssm::k_mmerge<16>, g, b, 0, s, M);
         else hipLaunchKernelGGL(ssm::k_mmerge<ssm::MKMAX>, g, b, 0, s, M);
     }
-    if (out_lcp) hipLaunchKernelGGL(ssm::k_mseam, dim3((L.nsamp + 63) / 64), dim3(64), 0, s, M);
+    if (out_lcp) hipLaunchKernelGGL(ssm::k_mseam, dim3((L.nsamp + L.xcap + 63) / 64), dim3(64), 0, s, M);
     ctx->last_ws = ws;
     return hipGetLastError() == hipSuccess ? SSORT_OK : SSORT_EDEVICE;
 }

@@ -30,17 +30,31 @@ constexpr uint32_t WAITING = 0xFFFFFFFEu;   // tree build: no player has reached
 // one 32-bit entry: LCPs up to HMASK - 8 (about 16 MiB) are supported.
 constexpr uint32_t HMASK = 0xFFFFFFu;
 
+// An input element as the merge reads it: its string (index, start,
+// length), its LCP with the run's previous element and the 8 characters at
+// that LCP, in one 32-byte entry, so that a lane advancing through K runs
+// streams through K arrays instead of 3K.
+struct __align__(32) MEnt {
+    uint64_t c;              // 8 characters at the LCP (the run's first element: at 0)
+    uint64_t st;
+    uint32_t id, h, ln, pad;
+};
+
 struct MergeParams {
     Strs S;
     uint32_t rb[MKMAX + 1];  // run boundaries
     const uint32_t *pin;     // runs of string indices
     const uint32_t *hin;     // their LCP arrays (entry at a run's start ignored)
     uint32_t *pout, *hout;
-    uint64_t *cache;         // 8 characters of each input string at its LCP
-    uint32_t *cuts;          // (nsamp + 1) rows of K cuts, in sample order
+    MEnt *ent;               // per input element, everything a merge step reads
+    uint32_t *cuts;          // rows of K cuts: nsamp in sample order, the run ends, then the split rows
+    uint32_t *ja, *jb;       // merge jobs: from cut row ja[s] to cut row jb[s]
     unsigned long long *err;
     unsigned long long *next_job;   // next merge job to claim
+    unsigned long long *nsplit;     // split rows handed out
     uint32_t K, n, g, nsamp;
+    uint32_t lcap;           // jobs longer than this are split
+    uint32_t xcap;           // split rows the workspace holds (n / lcap + 1)
 };
 
 // Start and length of string id.
@@ -54,37 +68,32 @@ __device__ __forceinline__ void str_ref(const MergeParams &M, uint32_t id, uint6
     *ln = (uint32_t)l;
 }
 
-__device__ __forceinline__ uint64_t str_key(const MergeParams &M, uint32_t id, uint32_t h) {
-    uint64_t st;
-    uint32_t ln;
-    str_ref(M, id, &st, &ln);
-    return key_at(M.S.chars, M.S.nchars, st, ln, h);
-}
-
-// Compare strings a and b that agree on [0, d): returns their LCP and
-// whether a < b (equal strings: by index), and in *lw the loser's characters
-// at the LCP (the word's leading *lv of them valid), taken from the bytes
-// just compared.  Both strings are located once, then compared 32 characters
-// (four independent 8-byte loads each) a trip.
-__device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, uint32_t b, uint32_t d, bool *a_less,
-                                             uint64_t *lw, uint32_t *lv) {
-    uint64_t sa, sb;
-    uint32_t la, lb;
-    str_ref(M, a, &sa, &la);
-    str_ref(M, b, &sb, &lb);
-    for (uint32_t l = d;; l += 32) {
-        uint64_t ka[4], kb[4];
+// Compare strings a and b (located at sa, sb with lengths la, lb) that agree
+// on [0, d): returns their LCP and whether a < b (equal strings: by index),
+// and in *lw the loser's characters at the LCP (the word's leading *lv of them
+// valid), taken from the bytes just compared.  64 characters (eight
+// independent 8-byte loads per string) a trip.
+__device__ __forceinline__ uint32_t cmp_at(const MergeParams &M, uint32_t a, uint64_t sa, uint32_t la, uint32_t b,
+                                           uint64_t sb, uint32_t lb, uint32_t d, bool *a_less, uint64_t *lw,
+                                           uint32_t *lv) {
+    for (uint32_t l = d;; l += 64) {
+        uint64_t ka[8], kb[8];
         ssd::keys32_at(M.S.chars, M.S.nchars, sa, la, l, ka);
+        ssd::keys32_at(M.S.chars, M.S.nchars, sa, la, l + 32, ka + 4);
         ssd::keys32_at(M.S.chars, M.S.nchars, sb, lb, l, kb);
+        ssd::keys32_at(M.S.chars, M.S.nchars, sb, lb, l + 32, kb + 4);
         // the first word that differs or ends both strings (selects only:
         // no indexing of the word arrays by a computed index)
-        uint32_t i = 4;
+        uint32_t i = 8;
 #pragma unroll
-        for (int t = 3; t >= 0; --t)
+        for (int t = 7; t >= 0; --t)
             if (ka[t] != kb[t] || (ka[t] & 0xFF) == 0) i = (uint32_t)t;
-        if (i == 4) continue;
+        if (i == 8) continue;
         auto pick = [](const uint64_t *k, uint32_t j) -> uint64_t {
-            return j == 0 ? k[0] : j == 1 ? k[1] : j == 2 ? k[2] : j == 3 ? k[3] : 0ull;
+            uint64_t r = 0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) r = j == (uint32_t)t ? k[t] : r;
+            return r;
         };
         const uint64_t xa = pick(ka, i), xb = pick(kb, i);
         if (xa == xb) {   // both end in this word: equal strings
@@ -100,19 +109,22 @@ __device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, u
         const uint64_t w0 = al ? xb : xa;
         const uint64_t w1 = al ? pick(kb, i + 1) : pick(ka, i + 1);
         *lw = e ? (w0 << (8 * e)) | (w1 >> (64 - 8 * e)) : w0;
-        *lv = (i + 1 < 4 || e == 0) ? 8u : 8u - e;
+        *lv = (i + 1 < 8 || e == 0) ? 8u : 8u - e;
         return l + 8 * i + e;
     }
 }
 
+// The same for strings given by their indices.
 __device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, uint32_t b, uint32_t d, bool *a_less) {
-    uint64_t w;
-    uint32_t v;
-    return cmp_from(M, a, b, d, a_less, &w, &v);
+    uint64_t sa, sb, w;
+    uint32_t la, lb, v;
+    str_ref(M, a, &sa, &la);
+    str_ref(M, b, &sb, &lb);
+    return cmp_at(M, a, sa, la, b, sb, lb, d, a_less, &w, &v);
 }
 
 // 8 characters at the LCP position of every input element (the run's first
-// element: at 0).
+// element: at 0), and its string's start, length and index.
 __global__ void k_mcache(MergeParams M) {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < M.n; p += gridDim.x * blockDim.x) {
         bool first = false;
@@ -121,10 +133,20 @@ __global__ void k_mcache(MergeParams M) {
         // the set ends the merge with a device error (they check it first)
         if (M.pin[p] >= M.S.n || (!first && M.hin[p] > HMASK - 8)) {
             atomicOr(M.err, ssd::ERR_MERGE);
-            M.cache[p] = 0;
             continue;
         }
-        M.cache[p] = str_key(M, M.pin[p], first ? 0u : M.hin[p]);
+        uint64_t st;
+        uint32_t ln;
+        const uint32_t id = M.pin[p], h = first ? 0u : M.hin[p];
+        str_ref(M, id, &st, &ln);
+        MEnt e;
+        e.c = key_at(M.S.chars, M.S.nchars, st, ln, h);
+        e.st = st;
+        e.id = id;
+        e.h = h;
+        e.ln = ln;
+        e.pad = 0;
+        M.ent[p] = e;
     }
 }
 
@@ -148,7 +170,8 @@ __global__ void k_msample(MergeParams M) {
     // which run and position: samples of run k are numbered from the
     // running total of earlier runs' samples
     bool live = t < M.nsamp;
-    uint32_t k = 0, pos = 0, sid = 0;
+    uint32_t k = 0, pos = 0;
+    MEnt sr;
     if (live) {
         uint32_t base = 0;
         for (; k < M.K; ++k) {
@@ -159,7 +182,7 @@ __global__ void k_msample(MergeParams M) {
         live = k < M.K;
         if (live) {
             pos = (t - base) * M.g;
-            sid = M.pin[M.rb[k] + pos];
+            sr = M.ent[M.rb[k] + pos];
         }
     }
     const bool mine = live && r < M.K;
@@ -168,12 +191,15 @@ __global__ void k_msample(MergeParams M) {
         if (r == k) {
             c = pos;
         } else {
-            const uint32_t *run = M.pin + M.rb[r];
+            const MEnt *run = M.ent + M.rb[r];
             uint32_t lo = 0, hi = M.rb[r + 1] - M.rb[r], llo = 0, lhi = 0;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
                 bool mid_less;
-                const uint32_t l = cmp_from(M, run[mid], sid, min(llo, lhi), &mid_less);
+                const MEnt &rm = run[mid];
+                uint64_t lw;
+                uint32_t lv;
+                const uint32_t l = cmp_at(M, rm.id, rm.st, rm.ln, sr.id, sr.st, sr.ln, min(llo, lhi), &mid_less, &lw, &lv);
                 if (mid_less) {
                     lo = mid + 1;
                     llo = l;
@@ -195,17 +221,120 @@ __global__ void k_msample(MergeParams M) {
     M.cuts[(size_t)order * M.K + r] = c;
 }
 
+// Jobs between consecutive samples vary in length (about exponentially
+// around g, the longest several times g), and the merge takes as long as its
+// longest job: a job longer than lcap is split into p = ceil(len / lcap)
+// parts at elements of its longest run (evenly spaced in that run's range),
+// each element's cut in every other run found by the same LCP-accelerated
+// binary search as the samples', inside the job's range.  One lane group of
+// KP lanes per job, lane r for run r.  The job list: job j is rows (j, j+1)
+// unsplit, else (j, x_1), (x_1, x_2), ..., (x_{p-1}, j+1) with the split rows
+// x_t taken from a shared counter; row nsamp holds the run ends.
+__global__ void k_msplit(MergeParams M) {
+    if (*M.err) return;
+    uint32_t KP = 1;
+    while (KP < M.K) KP <<= 1;
+    const uint32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t j = gt / KP, r = gt % KP;
+    const bool live = j < M.nsamp;
+    const bool mine = live && r < M.K;
+    const uint32_t K = M.K;
+    if (j == 0 && mine) M.cuts[(size_t)M.nsamp * K + r] = M.rb[r + 1] - M.rb[r];
+    uint32_t a = 0, b = 0;
+    bool bad = false;
+    if (mine) {
+        a = M.cuts[(size_t)j * K + r];
+        b = (j + 1 < M.nsamp) ? M.cuts[(size_t)(j + 1) * K + r] : M.rb[r + 1] - M.rb[r];
+        bad = a == SENT || b == SENT || a > b || b > M.rb[r + 1] - M.rb[r];
+    }
+    // the group's job length and its longest run (lowest run on ties)
+    uint32_t d = (mine && !bad) ? min(b - a, 1u << 26) : 0u;
+    uint32_t len = d;
+    uint32_t best = (d << 5) | (31u - (r & 31u));
+    for (uint32_t o = 1; o < KP; o <<= 1) {
+        len += (uint32_t)__shfl_xor((int)len, (int)o, 64);
+        best = max(best, (uint32_t)__shfl_xor((int)best, (int)o, 64));
+    }
+    uint32_t nbad = bad ? 1u : 0u;
+    for (uint32_t o = 1; o < KP; o <<= 1) nbad += (uint32_t)__shfl_xor((int)nbad, (int)o, 64);
+    if (!live) return;
+    const uint32_t rs = 31u - (best & 31u), ds = best >> 5;
+    uint32_t parts = (len + M.lcap - 1) / M.lcap;
+    parts = min(parts, ds);   // split elements distinct in the longest run
+    if (nbad || parts <= 1) {
+        // unsplit (a bad row is reported by the merge, which checks every row)
+        if (r == 0) {
+            M.ja[j] = j;
+            M.jb[j] = j + 1;
+        }
+        return;
+    }
+    unsigned long long x0 = 0;
+    if (r == 0) x0 = __hip_atomic_fetch_add(M.nsplit, (unsigned long long)(parts - 1), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    x0 = (unsigned long long)__shfl((long long)x0, (int)(threadIdx.x & 63u & ~(KP - 1)), 64);
+    if (x0 + parts - 1 > M.xcap) {
+        if (r == 0) atomicOr(M.err, ssd::ERR_MERGE);
+        return;
+    }
+    const uint32_t row0 = M.nsamp + 1 + (uint32_t)x0;   // split row of part 1
+    const uint32_t a_s = __shfl((int)a, (int)((threadIdx.x & 63u & ~(KP - 1)) + rs), 64);
+    for (uint32_t t = 1; t < parts; ++t) {
+        const uint32_t sp = a_s + (uint32_t)(((uint64_t)t * ds) / parts);   // split element's place in run rs
+        const MEnt sr = M.ent[M.rb[rs] + sp];
+        if (mine) {
+            uint32_t c;
+            if (r == rs) {
+                c = sp;
+            } else {
+                const MEnt *run = M.ent + M.rb[r];
+                uint32_t lo = a, hi = b, llo = 0, lhi = 0;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    bool mid_less;
+                    const MEnt &rm = run[mid];
+                    uint64_t lw;
+                    uint32_t lv;
+                    const uint32_t l = cmp_at(M, rm.id, rm.st, rm.ln, sr.id, sr.st, sr.ln, min(llo, lhi), &mid_less,
+                                              &lw, &lv);
+                    if (mid_less) {
+                        lo = mid + 1;
+                        llo = l;
+                    } else {
+                        hi = mid;
+                        lhi = l;
+                    }
+                }
+                c = lo;
+            }
+            M.cuts[(size_t)(row0 + t - 1) * K + r] = c;
+        }
+    }
+    if (r == 0) {
+        M.ja[j] = j;
+        M.jb[j] = row0;
+        for (uint32_t t = 1; t < parts; ++t) {
+            const uint32_t s = M.nsamp + (uint32_t)x0 + t - 1;   // job slot of part t + 1
+            M.ja[s] = row0 + t - 1;
+            M.jb[s] = t + 1 < parts ? row0 + t : j + 1;
+        }
+    }
+}
+
 // Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run, its
-// string id, its LCP with the winner of that game, and its 8 characters at
-// that LCP.  A loser's run does not advance while it sits in the tree, so the
-// id stays valid there and the replay reads no run position from global
-// memory.  KM, a power of two >= K, sizes the arrays: 28 * KM bytes per thread, so a
-// tree sized for the launch's K (not the largest) keeps more workgroups
-// resident per CU.
+// string (index, start, length), its LCP with the winner of that game, and
+// its 8 characters at that LCP.  A loser's run does not advance while it sits
+// in the tree, so its string stays valid there: the replay reads no run
+// position from global memory, and a game that compares strings reads their
+// characters directly.  KM, a power of two >= K, sizes the arrays: 40 * KM
+// bytes per thread, so a tree sized for the launch's K (not the largest)
+// keeps more workgroups resident per CU.
 template <int KM>
 struct MergeLDS {
+    uint64_t st[KM][MNT];   // the loser's string: start
     uint32_t y[KM][MNT];
     uint32_t yi[KM][MNT];   // string id of the loser's current element
+    uint32_t ln[KM][MNT];   // and length
     uint32_t h[KM][MNT];    // its LCP with the game's winner | valid cached characters << 24
     uint64_t c[KM][MNT];
     uint32_t pos[KM][MNT];   // next element of each run (absolute)
@@ -223,8 +352,9 @@ __device__ __forceinline__ uint32_t hv_pack(uint32_t h, uint32_t v) { return h |
 // characters decide, the loser's word is shifted to its new LCP and keeps the
 // rest of its valid characters, so the strings themselves are read only when
 // every valid cached character is equal.
-__device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t xid, uint32_t hx, uint64_t cx,
-                                     uint32_t y, uint32_t yid, uint32_t hy, uint64_t cy, uint32_t *lh, uint64_t *lc) {
+__device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t xid, uint64_t xs, uint32_t xl,
+                                     uint32_t hx, uint64_t cx, uint32_t y, uint32_t yid, uint64_t ys, uint32_t yl,
+                                     uint32_t hy, uint64_t cy, uint32_t *lh, uint64_t *lc) {
     if (y == SENT) {
         *lh = hy;
         *lc = cy;
@@ -265,7 +395,7 @@ __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t 
         } else {
             uint64_t lw;
             uint32_t lv;
-            uint32_t l = cmp_from(M, xid, yid, lx + m, &x_less, &lw, &lv);
+            uint32_t l = cmp_at(M, xid, xs, xl, yid, ys, yl, lx + m, &x_less, &lw, &lv);
             if (l > HMASK - 8) {   // beyond the packed LCP range: a device error, never a wrong order
                 atomicOr(M.err, ssd::ERR_MERGE);
                 l = HMASK - 8;
@@ -295,23 +425,47 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         atomicOr(M.err, ssd::ERR_MERGE);
         return;
     }
-    // Jobs are claimed one at a time from a shared counter: their lengths
-    // vary (about exponentially around g), and a wave that held one job per
-    // lane would run as long as its longest job.
+    // Jobs are claimed one at a time from a shared counter, and a lane that
+    // finishes its job claims the next one inside the same loop: job lengths
+    // vary (about exponentially around g), and lanes that merged their jobs
+    // in lockstep would hold their wave for its longest job each time.  An
+    // iteration either starts a job (claim, cut checks, tree build) or emits
+    // one output and replays the winner's path.
+    uint32_t out = 0;              // next output position of the lane's job
+    uint32_t w = SENT, hw = 0, wid = 0;
+    bool first = true;             // the next output is its job's first
     for (;;) {
-    const uint32_t j = (uint32_t)min(__hip_atomic_fetch_add(M.next_job, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                                     (unsigned long long)M.nsamp);
-    if (j >= M.nsamp || *M.err) return;
-    // this job: for each run, the elements between cut rows j and j+1; a
+    if (w == SENT) {
+    const uint32_t njobs = M.nsamp + (uint32_t)min(*M.nsplit, (unsigned long long)M.xcap);
+    // the lanes that need a job in this iteration claim consecutive ones
+    // with one atomic (a counter that every lane hit on its own would
+    // serialise over a hundred thousand of them at the start)
+    const uint64_t need = __ballot(1);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+    const int lead = __builtin_ctzll(need);
+    unsigned long long base = 0;
+    if (rank == 0)
+        base = __hip_atomic_fetch_add(M.next_job, (unsigned long long)__popcll(need), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    base = (unsigned long long)__shfl((long long)base, lead, 64);
+    const uint32_t j = (uint32_t)min(base + rank, (unsigned long long)njobs);
+    if (j >= njobs || *M.err) return;
+    // this job: for each run, the elements between its two cut rows; a
     // row the sample search left unwritten (two samples of the same rank:
     // runs that are not sorted by (string, index), or an index in two runs)
     // or cuts out of order end the merge with a device error, never an access
-    uint32_t out = 0, len = 0;
+    const uint32_t ra = M.ja[j], rb = M.jb[j];
+    if (ra > M.nsamp + M.xcap || rb > M.nsamp + M.xcap) {
+        atomicOr(M.err, ssd::ERR_MERGE);
+        return;
+    }
+    uint32_t len = 0;
+    out = 0;
     bool bad = false;
     for (uint32_t r = 0; r < KP; ++r) {
         if (r < K) {
-            const uint32_t a = M.cuts[(size_t)j * K + r];
-            const uint32_t b = (j + 1 < M.nsamp) ? M.cuts[(size_t)(j + 1) * K + r] : M.rb[r + 1] - M.rb[r];
+            const uint32_t a = M.cuts[(size_t)ra * K + r];
+            const uint32_t b = M.cuts[(size_t)rb * K + r];
             bad |= a == SENT || b == SENT || a > b || b > M.rb[r + 1] - M.rb[r];
             if (bad) break;
             L.pos[r][me] = M.rb[r] + a;
@@ -322,8 +476,8 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             L.pos[r][me] = L.end[r][me] = 0;
         }
     }
-    // jobs tile the output: job 0 starts at 0 and job j+1 where job j ends,
-    // so every output position is written once
+    // jobs tile the output: job 0 starts at 0 and every other job where
+    // another one ends, so every output position is written once
     if (bad || (j == 0 && out != 0) || out > M.n || len > M.n - out) {
         atomicOr(M.err, ssd::ERR_MERGE);
         return;
@@ -339,15 +493,17 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     // passes the root is the first winner.  Only the node arrays in LDS and
     // the climbing player's registers are used.
     for (uint32_t v = 1; v < KP; ++v) L.y[v][me] = WAITING;
-    uint32_t w = SENT, hw = 0, wid = 0;
     for (uint32_t r = 0; r < KP; ++r) {
-        uint32_t x = SENT, xid = 0, hx = 0;
-        uint64_t cx = 0;
+        uint32_t x = SENT, xid = 0, hx = 0, xl = 0;
+        uint64_t cx = 0, xs = 0;
         if (r < K && L.pos[r][me] < L.end[r][me]) {
+            const MEnt &e = M.ent[L.pos[r][me]];
             x = r;
-            xid = M.pin[L.pos[r][me]];
+            xid = e.id;
+            xs = e.st;
+            xl = e.ln;
             hx = hv_pack(0, 8);
-            cx = str_key(M, xid, 0);
+            cx = key_at(M.S.chars, M.S.nchars, xs, xl, 0);
         }
         bool waits = false;
         for (uint32_t v = (KP + r) >> 1; v >= 1; v >>= 1) {
@@ -355,24 +511,28 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             if (y == WAITING) {
                 L.y[v][me] = x;
                 L.yi[v][me] = xid;
+                L.st[v][me] = xs;
+                L.ln[v][me] = xl;
                 L.h[v][me] = hx;
                 L.c[v][me] = cx;
                 waits = true;
                 break;
             }
-            const uint32_t yid = L.yi[v][me];
+            const uint32_t yid = L.yi[v][me], yl = L.ln[v][me];
+            const uint64_t ys = L.st[v][me];
             const uint32_t hy = L.h[v][me];
             const uint64_t cy = L.c[v][me];
             uint32_t lh;
             uint64_t lc;
-            if (game(M, x, xid, hx, cx, y, yid, hy, cy, &lh, &lc)) {
-                L.y[v][me] = y;
-                L.yi[v][me] = yid;
-            } else {
+            if (!game(M, x, xid, xs, xl, hx, cx, y, yid, ys, yl, hy, cy, &lh, &lc)) {
                 L.y[v][me] = x;
                 L.yi[v][me] = xid;
+                L.st[v][me] = xs;
+                L.ln[v][me] = xl;
                 x = y;
                 xid = yid;
+                xs = ys;
+                xl = yl;
                 hx = hy;
                 cx = cy;
             }
@@ -385,63 +545,71 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             hw = hx;
         }
     }
-    bool first = true;
-    while (w != SENT) {
-        const uint32_t p = L.pos[w][me];
-        M.pout[out] = wid;
-        if (!first && M.hout) M.hout[out] = hw & HMASK;
-        first = false;
-        ++out;
-        // the winner's run advances; its next element's LCP with the string
-        // just written is the run's own LCP entry, its cached characters too
-        L.pos[w][me] = p + 1;
-        uint32_t x = w, hx = 0;
-        uint64_t cx = 0;
-        uint32_t xid = 0;
-        if (p + 1 < L.end[w][me]) {
-            hx = hv_pack(M.hin[p + 1], 8);
-            cx = M.cache[p + 1];
-            xid = M.pin[p + 1];
-        } else {
-            x = SENT;
-        }
-        for (uint32_t v = (KP + w) >> 1; v >= 1; v >>= 1) {
-            const uint32_t y = L.y[v][me];
-            const uint32_t yid = L.yi[v][me];
-            uint32_t lh;
-            uint64_t lc;
-            const bool xw = game(M, x, xid, hx, cx, y, yid, L.h[v][me], L.c[v][me], &lh, &lc);
-            if (!xw) {
-                L.y[v][me] = x;
-                L.yi[v][me] = xid;
-                x = y;
-                xid = yid;
-                hx = L.h[v][me];
-                cx = L.c[v][me];
-            } else {
-                L.y[v][me] = y;
-            }
-            L.h[v][me] = lh;
-            L.c[v][me] = lc;
-        }
-        w = x;
-        wid = xid;
-        hw = hx;
+    first = true;
+    continue;   // an empty job leaves w = SENT: claim the next
     }
+    const uint32_t p = L.pos[w][me];
+    M.pout[out] = wid;
+    if (!first && M.hout) M.hout[out] = hw & HMASK;
+    first = false;
+    ++out;
+    // the winner's run advances; its next element's LCP with the string
+    // just written is the run's own LCP entry, its cached characters too
+    L.pos[w][me] = p + 1;
+    uint32_t x = w, hx = 0, xid = 0, xl = 0;
+    uint64_t cx = 0, xs = 0;
+    if (p + 1 < L.end[w][me]) {
+        const MEnt e = M.ent[p + 1];
+        hx = hv_pack(e.h, 8);
+        cx = e.c;
+        xid = e.id;
+        xs = e.st;
+        xl = e.ln;
+    } else {
+        x = SENT;
+    }
+    for (uint32_t v = (KP + w) >> 1; v >= 1; v >>= 1) {
+        const uint32_t y = L.y[v][me];
+        const uint32_t yid = L.yi[v][me], yl = L.ln[v][me];
+        const uint64_t ys = L.st[v][me];
+        uint32_t lh;
+        uint64_t lc;
+        const uint32_t hy = L.h[v][me];
+        const uint64_t cy = L.c[v][me];
+        if (!game(M, x, xid, xs, xl, hx, cx, y, yid, ys, yl, hy, cy, &lh, &lc)) {
+            L.y[v][me] = x;
+            L.yi[v][me] = xid;
+            L.st[v][me] = xs;
+            L.ln[v][me] = xl;
+            x = y;
+            xid = yid;
+            xs = ys;
+            xl = yl;
+            hx = hy;
+            cx = cy;
+        }
+        L.h[v][me] = lh;
+        L.c[v][me] = lc;
+    }
+    w = x;
+    wid = xid;
+    hw = hx;
     }
 }
 
 // LCP between the first output of each job and the string before it (after
-// k_mmerge has checked every cut row: it runs only without a device error).
+// k_mmerge has checked every job's cut rows: it runs only without a device
+// error).
 __global__ void k_mseam(MergeParams M) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M.nsamp || *M.err) return;
-    uint32_t q = 0;
-    for (uint32_t r = 0; r < M.K; ++r) q += M.cuts[(size_t)j * M.K + r];
-    uint32_t qe = M.n;
-    if (j + 1 < M.nsamp) {
-        qe = 0;
-        for (uint32_t r = 0; r < M.K; ++r) qe += M.cuts[(size_t)(j + 1) * M.K + r];
+    if (*M.err) return;
+    const uint32_t njobs = M.nsamp + (uint32_t)min(*M.nsplit, (unsigned long long)M.xcap);
+    if (j >= njobs) return;
+    const uint32_t ra = M.ja[j], rb = M.jb[j];
+    uint32_t q = 0, qe = 0;
+    for (uint32_t r = 0; r < M.K; ++r) {
+        q += M.cuts[(size_t)ra * M.K + r];
+        qe += M.cuts[(size_t)rb * M.K + r];
     }
     if (q >= qe || qe > M.n) return;
     if (q == 0) {
@@ -461,6 +629,7 @@ __global__ void k_mreset(MergeParams M) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *M.err = 0;
         *M.next_job = 0;
+        *M.nsplit = 0;
     }
 }
 
