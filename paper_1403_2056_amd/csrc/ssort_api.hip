@@ -504,7 +504,7 @@ constexpr uint32_t MERGE_G = 128;   // sample spacing: n / MERGE_G jobs of about
 constexpr uint32_t MERGE_LCAP = 128;   // longer jobs are split
 
 struct MergeLayout {
-    size_t ctl, ent, cuts, ja, jb, total;
+    size_t ctl, ent, cuts, cuth, cutc, ja, jb, total;
     uint32_t nsamp, xcap;
 };
 
@@ -518,8 +518,13 @@ MergeLayout merge_layout(uint32_t n, const uint32_t *run_begin, uint32_t K) {
     L.ent = off;
     off = align_up(off + sizeof(ssm::MEnt) * (size_t)n, 256);
     L.xcap = n / MERGE_LCAP + 1;
+    const size_t rows = (size_t)(L.nsamp + 1 + L.xcap) * K;
     L.cuts = off;
-    off = align_up(off + 4 * (size_t)(L.nsamp + 1 + L.xcap) * K, 256);
+    off = align_up(off + 4 * rows, 256);
+    L.cuth = off;
+    off = align_up(off + 4 * rows, 256);
+    L.cutc = off;
+    off = align_up(off + 8 * rows, 256);
     L.ja = off;
     off = align_up(off + 4 * (size_t)(L.nsamp + L.xcap), 256);
     L.jb = off;
@@ -575,6 +580,8 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
     M.nsplit = &((Ctl *)(w + L.ctl))->tail;
     M.ent = (ssm::MEnt *)(w + L.ent);
     M.cuts = (uint32_t *)(w + L.cuts);
+    M.cuth = (uint32_t *)(w + L.cuth);
+    M.cutc = (uint64_t *)(w + L.cutc);
     M.ja = (uint32_t *)(w + L.ja);
     M.jb = (uint32_t *)(w + L.jb);
     M.K = K;

@@ -29,6 +29,9 @@ constexpr uint32_t WAITING = 0xFFFFFFFEu;   // tree build: no player has reached
 // A player's LCP and the number of valid characters in its cached word share
 // one 32-bit entry: LCPs up to HMASK - 8 (about 16 MiB) are supported.
 constexpr uint32_t HMASK = 0xFFFFFFu;
+constexpr uint32_t NOREF = 0xFFFFFFFFu;   // a cut's LCP with its row's string is not available
+
+__device__ __forceinline__ uint32_t hv_pack(uint32_t h, uint32_t v) { return h | (v << 24); }
 
 // An input element as the merge reads it: its string (index, start,
 // length), its LCP with the run's previous element and the 8 characters at
@@ -48,6 +51,11 @@ struct MergeParams {
     uint32_t *pout, *hout;
     MEnt *ent;               // per input element, everything a merge step reads
     uint32_t *cuts;          // rows of K cuts: nsamp in sample order, the run ends, then the split rows
+    // per cut: the LCP of the element at the cut with the row's string (the
+    // sample or split element) and the valid count packed as in the tree, or
+    // NOREF; and that element's characters at the LCP
+    uint32_t *cuth;
+    uint64_t *cutc;
     uint32_t *ja, *jb;       // merge jobs: from cut row ja[s] to cut row jb[s]
     unsigned long long *err;
     unsigned long long *next_job;   // next merge job to claim
@@ -186,13 +194,16 @@ __global__ void k_msample(MergeParams M) {
         }
     }
     const bool mine = live && r < M.K;
-    uint32_t c = 0;
+    uint32_t c = 0, ch = NOREF;
+    uint64_t cc = 0;
     if (mine) {
         if (r == k) {
             c = pos;
+            if (sr.ln <= HMASK - 8) ch = hv_pack(sr.ln, 8);   // the sample itself: its whole length, then the end
         } else {
             const MEnt *run = M.ent + M.rb[r];
-            uint32_t lo = 0, hi = M.rb[r + 1] - M.rb[r], llo = 0, lhi = 0;
+            uint32_t lo = 0, hi = M.rb[r + 1] - M.rb[r], llo = 0, lhi = 0, vhi = 0;
+            uint64_t whi = 0;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
                 bool mid_less;
@@ -204,11 +215,19 @@ __global__ void k_msample(MergeParams M) {
                     lo = mid + 1;
                     llo = l;
                 } else {
+                    // the element is the larger: its characters at the LCP
                     hi = mid;
                     lhi = l;
+                    whi = lw;
+                    vhi = lv;
                 }
             }
             c = lo;
+            // the element at the cut was compared last when hi came down to it
+            if (c < M.rb[r + 1] - M.rb[r] && lhi <= HMASK - 8) {
+                ch = hv_pack(lhi, vhi);
+                cc = whi;
+            }
         }
     }
     uint32_t order = mine ? samples_below(c, M.g) : 0u;
@@ -219,6 +238,8 @@ __global__ void k_msample(MergeParams M) {
         return;
     }
     M.cuts[(size_t)order * M.K + r] = c;
+    M.cuth[(size_t)order * M.K + r] = ch;
+    M.cutc[(size_t)order * M.K + r] = cc;
 }
 
 // Jobs between consecutive samples vary in length (about exponentially
@@ -283,12 +304,15 @@ __global__ void k_msplit(MergeParams M) {
         const uint32_t sp = a_s + (uint32_t)(((uint64_t)t * ds) / parts);   // split element's place in run rs
         const MEnt sr = M.ent[M.rb[rs] + sp];
         if (mine) {
-            uint32_t c;
+            uint32_t c, ch = NOREF;
+            uint64_t cc = 0;
             if (r == rs) {
                 c = sp;
+                if (sr.ln <= HMASK - 8) ch = hv_pack(sr.ln, 8);
             } else {
                 const MEnt *run = M.ent + M.rb[r];
-                uint32_t lo = a, hi = b, llo = 0, lhi = 0;
+                uint32_t lo = a, hi = b, llo = 0, lhi = 0, vhi = 0;
+                uint64_t whi = 0;
                 while (lo < hi) {
                     const uint32_t mid = (lo + hi) >> 1;
                     bool mid_less;
@@ -303,11 +327,21 @@ __global__ void k_msplit(MergeParams M) {
                     } else {
                         hi = mid;
                         lhi = l;
+                        whi = lw;
+                        vhi = lv;
                     }
                 }
                 c = lo;
+                // (below b the element at the cut was compared: hi came down to it)
+                if (c < b && lhi <= HMASK - 8) {
+                    ch = hv_pack(lhi, vhi);
+                    cc = whi;
+                }
             }
-            M.cuts[(size_t)(row0 + t - 1) * K + r] = c;
+            const size_t q = (size_t)(row0 + t - 1) * K + r;
+            M.cuts[q] = c;
+            M.cuth[q] = ch;
+            M.cutc[q] = cc;
         }
     }
     if (r == 0) {
@@ -341,7 +375,6 @@ struct MergeLDS {
     uint32_t end[KM][MNT];
 };
 
-__device__ __forceinline__ uint32_t hv_pack(uint32_t h, uint32_t v) { return h | (v << 24); }
 
 // One game (Algorithm 2 with cached characters): the candidate (x, hx, cx)
 // against the node's loser (y, hy, cy), both with LCPs against the same
@@ -352,29 +385,32 @@ __device__ __forceinline__ uint32_t hv_pack(uint32_t h, uint32_t v) { return h |
 // characters decide, the loser's word is shifted to its new LCP and keeps the
 // rest of its valid characters, so the strings themselves are read only when
 // every valid cached character is equal.
-__device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t xid, uint64_t xs, uint32_t xl,
-                                     uint32_t hx, uint64_t cx, uint32_t y, uint32_t yid, uint64_t ys, uint32_t yl,
-                                     uint32_t hy, uint64_t cy, uint32_t *lh, uint64_t *lc) {
+// The part of a game decided without reading the strings: returns 0 when
+// the candidate wins, 1 when it loses (the loser's LCP and characters in
+// (lh, lc)), 2 when every valid cached character is equal and the strings
+// must be compared from *from on.
+__device__ __forceinline__ int game_pre(uint32_t x, uint32_t xid, uint32_t hx, uint64_t cx, uint32_t y, uint32_t yid,
+                                        uint32_t hy, uint64_t cy, uint32_t *lh, uint64_t *lc, uint32_t *from) {
     if (y == SENT) {
         *lh = hy;
         *lc = cy;
-        return true;
+        return 0;
     }
     if (x == SENT) {
         *lh = hx;
         *lc = cx;
-        return false;
+        return 1;
     }
     const uint32_t lx = hx & HMASK, ly = hy & HMASK;
     if (lx > ly) {   // the candidate agrees longer with p: it is smaller
         *lh = hy;
         *lc = cy;
-        return true;
+        return 0;
     }
     if (lx < ly) {
         *lh = hx;
         *lc = cx;
-        return false;
+        return 1;
     }
     // equal LCPs: compare characters from there, the valid cached ones first
     const uint32_t m = min(hx >> 24, hy >> 24);   // characters valid in both words
@@ -393,16 +429,8 @@ __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t 
             x_less = xid < yid;
             e = t;
         } else {
-            uint64_t lw;
-            uint32_t lv;
-            uint32_t l = cmp_at(M, xid, xs, xl, yid, ys, yl, lx + m, &x_less, &lw, &lv);
-            if (l > HMASK - 8) {   // beyond the packed LCP range: a device error, never a wrong order
-                atomicOr(M.err, ssd::ERR_MERGE);
-                l = HMASK - 8;
-            }
-            *lh = hv_pack(l, lv);
-            *lc = lw;
-            return x_less;
+            *from = lx + m;
+            return 2;
         }
     }
     // the loser keeps its characters after the first e
@@ -410,7 +438,33 @@ __device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t 
     const uint32_t vold = (x_less ? hy : hx) >> 24;
     *lh = hv_pack(lx + e, vold - e);
     *lc = e ? lold << (8 * e) : lold;
+    return x_less ? 0 : 1;
+}
+
+// The strings' part: compare from `from` on (Algorithm 2 with the LCP found).
+__device__ __forceinline__ bool game_str(const MergeParams &M, uint32_t xid, uint64_t xs, uint32_t xl, uint32_t yid,
+                                         uint64_t ys, uint32_t yl, uint32_t from, uint32_t *lh, uint64_t *lc) {
+    bool x_less;
+    uint64_t lw;
+    uint32_t lv;
+    uint32_t l = cmp_at(M, xid, xs, xl, yid, ys, yl, from, &x_less, &lw, &lv);
+    if (l > HMASK - 8) {   // beyond the packed LCP range: a device error, never a wrong order
+        atomicOr(M.err, ssd::ERR_MERGE);
+        l = HMASK - 8;
+    }
+    *lh = hv_pack(l, lv);
+    *lc = lw;
     return x_less;
+}
+
+// A whole game: true when the candidate wins.
+__device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t xid, uint64_t xs, uint32_t xl,
+                                     uint32_t hx, uint64_t cx, uint32_t y, uint32_t yid, uint64_t ys, uint32_t yl,
+                                     uint32_t hy, uint64_t cy, uint32_t *lh, uint64_t *lc) {
+    uint32_t from = 0;
+    const int d = game_pre(x, xid, hx, cx, y, yid, hy, cy, lh, lc, &from);
+    if (d != 2) return d == 0;
+    return game_str(M, xid, xs, xl, yid, ys, yl, from, lh, lc);
 }
 
 template <int KM>
@@ -426,16 +480,25 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         return;
     }
     // Jobs are claimed one at a time from a shared counter, and a lane that
-    // finishes its job claims the next one inside the same loop: job lengths
-    // vary (about exponentially around g), and lanes that merged their jobs
-    // in lockstep would hold their wave for its longest job each time.  An
-    // iteration either starts a job (claim, cut checks, tree build) or emits
-    // one output and replays the winner's path.
+    // finishes its job claims the next one inside the same loop (lanes that
+    // merged their jobs in lockstep would hold their wave for its longest
+    // job each time).  The candidate climbs the tree with the part of each
+    // game that needs no string; a lane whose game needs the strings stops
+    // at that node, and the comparison runs once per iteration for every
+    // lane stopped (inside the climb it would run, for the few lanes that
+    // need it, at every level, with the wave's other lanes waiting); the lane
+    // goes on climbing in the next iteration.
     uint32_t out = 0;              // next output position of the lane's job
-    uint32_t w = SENT, hw = 0, wid = 0;
+    // the candidate: its run x (SENT: exhausted), string, LCP with the last
+    // output (and valid count) and cached characters; v: the node it plays
+    // next, 0 once it has passed the root (it is the next output)
+    uint32_t x = SENT, xid = 0, xl = 0, hx = 0, v = 0;
+    uint64_t xs = 0, cx = 0;
     bool first = true;             // the next output is its job's first
     for (;;) {
-    if (w == SENT) {
+    if (v == 0) {
+    if (x == SENT) {
+    // the job is done (or none was claimed yet): the next one
     const uint32_t njobs = M.nsamp + (uint32_t)min(*M.nsplit, (unsigned long long)M.xcap);
     // the lanes that need a job in this iteration claim consecutive ones
     // with one atomic (a counter that every lane hit on its own would
@@ -482,17 +545,27 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         atomicOr(M.err, ssd::ERR_MERGE);
         return;
     }
-    // players: the runs' first elements of the job, LCP 0 against the empty
-    // string.  The tree is built by inserting them one after the other: a
-    // player climbs from its leaf, stops at the first node no player of the
-    // other subtree has reached yet (it waits there), and otherwise plays
-    // the waiting player, the loser staying at the node with its LCP against
-    // the winner.  Inserted left to right, each subtree is complete when its
-    // last player arrives, so every game is between the winners of two
-    // subtrees, both with LCPs against the empty string; the player that
-    // passes the root is the first winner.  Only the node arrays in LDS and
-    // the climbing player's registers are used.
-    for (uint32_t v = 1; v < KP; ++v) L.y[v][me] = WAITING;
+    // players: the runs' first elements of the job, with their LCPs against
+    // a string no larger than any of them (Algorithm 4 starts from the empty
+    // string): the job's lower row's string (its sample or split element),
+    // whose LCP with each cut element the search that placed the cut found,
+    // with the element's characters there, so that the first games are
+    // decided like the later ones, mostly without reading the strings; when
+    // one of them is missing (a string too long for the packed LCP), the
+    // empty string for every player.  The tree is built by inserting them
+    // one after the other: a player climbs from its leaf, stops at the first
+    // node no player of the other subtree has reached yet (it waits there),
+    // and otherwise plays the waiting player, the loser staying at the node
+    // with its LCP against the winner.  Inserted left to right, each subtree
+    // is complete when its last player arrives, so every game is between the
+    // winners of two subtrees, both with LCPs against the same string; the
+    // player that passes the root is the first winner.  Only the node arrays
+    // in LDS and the climbing player's registers are used.
+    bool ref = true;
+    for (uint32_t r = 0; r < K; ++r)
+        if (L.pos[r][me] < L.end[r][me] && M.cuth[(size_t)ra * K + r] == NOREF) ref = false;
+    for (uint32_t u = 1; u < KP; ++u) L.y[u][me] = WAITING;
+    uint32_t wn = SENT, widn = 0, hwn = 0;   // the first winner
     for (uint32_t r = 0; r < KP; ++r) {
         uint32_t x = SENT, xid = 0, hx = 0, xl = 0;
         uint64_t cx = 0, xs = 0;
@@ -502,8 +575,13 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             xid = e.id;
             xs = e.st;
             xl = e.ln;
-            hx = hv_pack(0, 8);
-            cx = key_at(M.S.chars, M.S.nchars, xs, xl, 0);
+            if (ref) {
+                hx = M.cuth[(size_t)ra * K + r];
+                cx = M.cutc[(size_t)ra * K + r];
+            } else {
+                hx = hv_pack(0, 8);
+                cx = key_at(M.S.chars, M.S.nchars, xs, xl, 0);
+            }
         }
         bool waits = false;
         for (uint32_t v = (KP + r) >> 1; v >= 1; v >>= 1) {
@@ -540,43 +618,80 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             L.c[v][me] = lc;
         }
         if (!waits) {
-            w = x;
-            wid = xid;
-            hw = hx;
+            wn = x;
+            widn = xid;
+            hwn = hx;
         }
     }
+    x = wn;
+    xid = widn;
+    hx = hwn;
     first = true;
-    continue;   // an empty job leaves w = SENT: claim the next
+    continue;   // an empty job leaves x = SENT: claim the next
     }
-    const uint32_t p = L.pos[w][me];
-    M.pout[out] = wid;
-    if (!first && M.hout) M.hout[out] = hw & HMASK;
+    // output the candidate; its run's next element climbs from the leaf: its
+    // LCP with the string just written is the run's own LCP entry, its
+    // cached characters too
+    const uint32_t run = x;
+    const uint32_t p = L.pos[run][me];
+    M.pout[out] = xid;
+    if (!first && M.hout) M.hout[out] = hx & HMASK;
     first = false;
     ++out;
-    // the winner's run advances; its next element's LCP with the string
-    // just written is the run's own LCP entry, its cached characters too
-    L.pos[w][me] = p + 1;
-    uint32_t x = w, hx = 0, xid = 0, xl = 0;
-    uint64_t cx = 0, xs = 0;
-    if (p + 1 < L.end[w][me]) {
+    L.pos[run][me] = p + 1;
+    if (p + 1 < L.end[run][me]) {
         const MEnt e = M.ent[p + 1];
-        hx = hv_pack(e.h, 8);
-        cx = e.c;
         xid = e.id;
         xs = e.st;
         xl = e.ln;
+        hx = hv_pack(e.h, 8);
+        cx = e.c;
     } else {
         x = SENT;
     }
-    for (uint32_t v = (KP + w) >> 1; v >= 1; v >>= 1) {
-        const uint32_t y = L.y[v][me];
-        const uint32_t yid = L.yi[v][me], yl = L.ln[v][me];
-        const uint64_t ys = L.st[v][me];
-        uint32_t lh;
-        uint64_t lc;
+    v = (KP + run) >> 1;
+    }
+    // climb while the games need no string
+    uint32_t from = 0;
+    bool stop = false;
+    while (v >= 1) {
+        const uint32_t y = L.y[v][me], yid = L.yi[v][me];
         const uint32_t hy = L.h[v][me];
         const uint64_t cy = L.c[v][me];
-        if (!game(M, x, xid, xs, xl, hx, cx, y, yid, ys, yl, hy, cy, &lh, &lc)) {
+        uint32_t lh;
+        uint64_t lc;
+        const int d = game_pre(x, xid, hx, cx, y, yid, hy, cy, &lh, &lc, &from);
+        if (d == 2) {
+            stop = true;
+            break;
+        }
+        if (d == 1) {
+            L.y[v][me] = x;
+            L.yi[v][me] = xid;
+            const uint64_t ys = L.st[v][me];
+            const uint32_t yl = L.ln[v][me];
+            L.st[v][me] = xs;
+            L.ln[v][me] = xl;
+            x = y;
+            xid = yid;
+            xs = ys;
+            xl = yl;
+            hx = hy;
+            cx = cy;
+        }
+        L.h[v][me] = lh;
+        L.c[v][me] = lc;
+        v >>= 1;
+    }
+    if (stop) {
+        // the game at node v compares the strings
+        const uint32_t y = L.y[v][me], yid = L.yi[v][me], yl = L.ln[v][me];
+        const uint64_t ys = L.st[v][me];
+        const uint32_t hy = L.h[v][me];
+        const uint64_t cy = L.c[v][me];
+        uint32_t lh;
+        uint64_t lc;
+        if (!game_str(M, xid, xs, xl, yid, ys, yl, from, &lh, &lc)) {
             L.y[v][me] = x;
             L.yi[v][me] = xid;
             L.st[v][me] = xs;
@@ -590,10 +705,8 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         }
         L.h[v][me] = lh;
         L.c[v][me] = lc;
+        v >>= 1;
     }
-    w = x;
-    wid = xid;
-    hw = hx;
     }
 }
 
