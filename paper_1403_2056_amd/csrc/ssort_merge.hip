@@ -76,59 +76,119 @@ __device__ __forceinline__ void str_ref(const MergeParams &M, uint32_t id, uint6
     *ln = (uint32_t)l;
 }
 
+// 64 characters of a string from depth h as raw words (the first character
+// in the low byte of w[0]), loaded from the at most nine aligned words that
+// hold them; *rem: the characters the string has from h (bytes of w past
+// them are not the string's).
+__device__ __forceinline__ void raw64(const uint8_t *chars, uint64_t nchars, uint64_t st, uint32_t ln, uint32_t h,
+                                      uint64_t w[8], uint32_t *rem) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w[j] = 0;
+    *rem = 0;
+    if (h >= ln) return;
+    const uint64_t p = st + h;
+    if (p >= nchars) return;
+    const uint32_t r = (uint32_t)min((uint64_t)(ln - h), nchars - p);
+    *rem = r;
+    const uint32_t sh = (uint32_t)((uintptr_t)(chars + p) & 7);
+    const uint64_t *a0 = reinterpret_cast<const uint64_t *>(chars + (p - sh));
+    const uint32_t nw = (sh + min(r, 64u) + 7) >> 3;   // words holding wanted bytes, 1..9
+    uint64_t a[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a[i] = (uint32_t)i < nw ? a0[i] : 0ull;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w[j] = sh ? (a[j] >> (8 * sh)) | (a[j + 1] << (64 - 8 * sh)) : a[j];
+}
+
 // Compare strings a and b (located at sa, sb with lengths la, lb) that agree
 // on [0, d): returns their LCP and whether a < b (equal strings: by index),
 // and in *lw the loser's characters at the LCP (the word's leading *lv of them
-// valid), taken from the bytes just compared.  64 characters (eight
-// independent 8-byte loads per string) a trip.
+// valid), taken from the bytes just compared.  64 characters of each string a
+// trip, compared as raw words (equality needs no byte order): only the first
+// differing word and the loser's new word are put in character order.
 __device__ __forceinline__ uint32_t cmp_at(const MergeParams &M, uint32_t a, uint64_t sa, uint32_t la, uint32_t b,
                                            uint64_t sb, uint32_t lb, uint32_t d, bool *a_less, uint64_t *lw,
                                            uint32_t *lv) {
+    // word j of a window (selects only: no indexing of the word arrays by a
+    // computed index); 0 past the window
+    auto pick = [](const uint64_t *k, uint32_t j) -> uint64_t {
+        uint64_t r = 0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) r = j == (uint32_t)t ? k[t] : r;
+        return r;
+    };
     for (uint32_t l = d;; l += 64) {
-        uint64_t ka[8], kb[8];
-        ssd::keys32_at(M.S.chars, M.S.nchars, sa, la, l, ka);
-        ssd::keys32_at(M.S.chars, M.S.nchars, sa, la, l + 32, ka + 4);
-        ssd::keys32_at(M.S.chars, M.S.nchars, sb, lb, l, kb);
-        ssd::keys32_at(M.S.chars, M.S.nchars, sb, lb, l + 32, kb + 4);
-        // the first word that differs or ends both strings (selects only:
-        // no indexing of the word arrays by a computed index)
+        uint64_t A[8], B[8];
+        uint32_t ra, rb;
+        raw64(M.S.chars, M.S.nchars, sa, la, l, A, &ra);
+        raw64(M.S.chars, M.S.nchars, sb, lb, l, B, &rb);
+        const uint32_t m = min(min(ra, rb), 64u);   // characters both have in the window
+        // the first word with a difference among them
         uint32_t i = 8;
+        uint64_t z = 0;
 #pragma unroll
-        for (int t = 7; t >= 0; --t)
-            if (ka[t] != kb[t] || (ka[t] & 0xFF) == 0) i = (uint32_t)t;
-        if (i == 8) continue;
-        auto pick = [](const uint64_t *k, uint32_t j) -> uint64_t {
-            uint64_t r = 0;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) r = j == (uint32_t)t ? k[t] : r;
-            return r;
-        };
-        const uint64_t xa = pick(ka, i), xb = pick(kb, i);
-        if (xa == xb) {   // both end in this word: equal strings
-            *a_less = a < b;
-            *lw = 0;   // past the end
-            *lv = 8;
-            return min(la, lb);
+        for (int t = 7; t >= 0; --t) {
+            const int r = (int)m - 8 * t;
+            const uint64_t mk = r >= 8 ? ~0ull : r <= 0 ? 0ull : ~0ull >> (64 - 8 * r);
+            const uint64_t zt = (A[t] ^ B[t]) & mk;
+            if (zt) {
+                i = (uint32_t)t;
+                z = zt;
+            }
         }
-        const bool al = xa < xb;
+        uint32_t pos;
+        bool al;
+        if (i < 8) {
+            const uint32_t bit = (uint32_t)__builtin_ctzll(z) & ~7u;
+            pos = 8 * i + (bit >> 3);
+            al = ((pick(A, i) >> bit) & 0xFF) < ((pick(B, i) >> bit) & 0xFF);
+        } else if (m < 64) {
+            // one string ends inside the window with no difference before
+            if (ra == rb) {   // both: equal strings
+                *a_less = a < b;
+                *lw = 0;   // past the end
+                *lv = 8;
+                return l + m;
+            }
+            al = ra < rb;   // the shorter is a prefix of the longer
+            pos = m;
+        } else {
+            continue;
+        }
         *a_less = al;
-        const uint32_t e = (uint32_t)(__clzll(xa ^ xb) >> 3);
-        // the loser's 8 characters from the difference on
-        const uint64_t w0 = al ? xb : xa;
-        const uint64_t w1 = al ? pick(kb, i + 1) : pick(ka, i + 1);
-        *lw = e ? (w0 << (8 * e)) | (w1 >> (64 - 8 * e)) : w0;
-        *lv = (i + 1 < 8 || e == 0) ? 8u : 8u - e;
-        return l + 8 * i + e;
+        // the loser's 8 characters from pos (it has at least one there), zero
+        // past its end; those past the window are unknown unless it ends
+        // inside the window
+        const uint32_t rl = al ? rb : ra;
+        const uint32_t j0 = pos >> 3, o = pos & 7;
+        const uint64_t u0 = al ? pick(B, j0) : pick(A, j0);
+        const uint64_t u1 = al ? pick(B, j0 + 1) : pick(A, j0 + 1);
+        uint64_t raw = o ? (u0 >> (8 * o)) | (u1 << (64 - 8 * o)) : u0;
+        const uint32_t left = rl - pos;
+        if (left < 8) raw &= ~0ull >> (64 - 8 * left);
+        *lw = __builtin_bswap64(raw);
+        *lv = (rl <= 64 || pos + 8 <= 64) ? 8u : 64u - pos;
+        return l + pos;
     }
 }
 
-// The same for strings given by their indices.
-__device__ __forceinline__ uint32_t cmp_from(const MergeParams &M, uint32_t a, uint32_t b, uint32_t d, bool *a_less) {
-    uint64_t sa, sb, w;
-    uint32_t la, lb, v;
+// LCP of the strings with indices a and b, compared 32 characters (four
+// big-endian 8-byte keys, zero past the end) a trip.
+__device__ __forceinline__ uint32_t lcp_of(const MergeParams &M, uint32_t a, uint32_t b) {
+    uint64_t sa, sb;
+    uint32_t la, lb;
     str_ref(M, a, &sa, &la);
     str_ref(M, b, &sb, &lb);
-    return cmp_at(M, a, sa, la, b, sb, lb, d, a_less, &w, &v);
+    for (uint32_t l = 0;; l += 32) {
+        uint64_t ka[4], kb[4];
+        ssd::keys32_at(M.S.chars, M.S.nchars, sa, la, l, ka);
+        ssd::keys32_at(M.S.chars, M.S.nchars, sb, lb, l, kb);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (ka[t] != kb[t]) return l + 8 * t + (uint32_t)(__clzll(ka[t] ^ kb[t]) >> 3);
+            if ((ka[t] & 0xFF) == 0) return min(la, lb);   // both end in this word: equal strings
+        }
+    }
 }
 
 // 8 characters at the LCP position of every input element (the run's first
@@ -729,8 +789,7 @@ __global__ void k_mseam(MergeParams M) {
         M.hout[0] = 0;
         return;
     }
-    bool less;
-    M.hout[q] = cmp_from(M, M.pout[q - 1], M.pout[q], 0, &less);
+    M.hout[q] = lcp_of(M, M.pout[q - 1], M.pout[q]);
 }
 
 // Clear the error word and mark every cut row unwritten (a kernel, not a
