@@ -504,7 +504,7 @@ constexpr uint32_t MERGE_G = 128;   // sample spacing: n / MERGE_G jobs of about
 constexpr uint32_t MERGE_LCAP = 128;   // longer jobs are split
 
 struct MergeLayout {
-    size_t ctl, ent, cuts, cuth, cutc, ja, jb, total;
+    size_t ctl, ent, cuts, cuth, cutc, ja, jb, xd, total;
     uint32_t nsamp, xcap;
 };
 
@@ -529,6 +529,8 @@ MergeLayout merge_layout(uint32_t n, const uint32_t *run_begin, uint32_t K) {
     off = align_up(off + 4 * (size_t)(L.nsamp + L.xcap), 256);
     L.jb = off;
     off = align_up(off + 4 * (size_t)(L.nsamp + L.xcap), 256);
+    L.xd = off;
+    off = align_up(off + 12 * (size_t)L.xcap, 256);
     L.total = off;
     return L;
 }
@@ -584,6 +586,7 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
     M.cutc = (uint64_t *)(w + L.cutc);
     M.ja = (uint32_t *)(w + L.ja);
     M.jb = (uint32_t *)(w + L.jb);
+    M.xd = (uint32_t *)(w + L.xd);
     M.K = K;
     M.n = n;
     M.g = MERGE_G;
@@ -598,6 +601,7 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
         while (kps < K) kps <<= 1;
         hipLaunchKernelGGL(ssm::k_msample, dim3((uint32_t)(((size_t)L.nsamp * kps + 63) / 64)), dim3(64), 0, s, M);
         hipLaunchKernelGGL(ssm::k_msplit, dim3((uint32_t)(((size_t)L.nsamp * kps + 63) / 64)), dim3(64), 0, s, M);
+        hipLaunchKernelGGL(ssm::k_msplit_rows, dim3((uint32_t)(((size_t)L.xcap * kps + 63) / 64)), dim3(64), 0, s, M);
     }
     {
         // the loser tree's LDS arrays sized for the smallest power of two >= K

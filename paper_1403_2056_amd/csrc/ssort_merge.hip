@@ -57,6 +57,7 @@ struct MergeParams {
     uint32_t *cuth;
     uint64_t *cutc;
     uint32_t *ja, *jb;       // merge jobs: from cut row ja[s] to cut row jb[s]
+    uint32_t *xd;            // per split row: its job, the job's longest run, the split element's place there
     unsigned long long *err;
     unsigned long long *next_job;   // next merge job to claim
     unsigned long long *nsplit;     // split rows handed out
@@ -338,71 +339,48 @@ __global__ void k_msplit(MergeParams M) {
     }
     uint32_t nbad = bad ? 1u : 0u;
     for (uint32_t o = 1; o < KP; o <<= 1) nbad += (uint32_t)__shfl_xor((int)nbad, (int)o, 64);
-    if (!live) return;
     const uint32_t rs = 31u - (best & 31u), ds = best >> 5;
     uint32_t parts = (len + M.lcap - 1) / M.lcap;
     parts = min(parts, ds);   // split elements distinct in the longest run
-    if (nbad || parts <= 1) {
-        // unsplit (a bad row is reported by the merge, which checks every row)
+    if (!live || nbad) parts = 0;   // (a bad row is reported by the merge, which checks every row)
+    // split rows for the wave's jobs with one atomic: an exclusive prefix
+    // sum of the group leaders' counts over the wave
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t mycnt = (r == 0 && parts > 1) ? parts - 1 : 0u;
+    uint32_t incl = mycnt;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const uint32_t wtot = (uint32_t)__shfl((int)incl, 63, 64);
+    unsigned long long wbase = 0;
+    if (lane == 63 && wtot)
+        wbase = __hip_atomic_fetch_add(M.nsplit, (unsigned long long)wtot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wbase = (unsigned long long)__shfl((long long)wbase, 63, 64);
+    const uint32_t excl = (uint32_t)__shfl((int)(incl - mycnt), (int)(lane & ~(KP - 1)), 64);
+    if (!live) return;
+    if (parts <= 1) {
+        // unsplit
         if (r == 0) {
             M.ja[j] = j;
             M.jb[j] = j + 1;
         }
         return;
     }
-    unsigned long long x0 = 0;
-    if (r == 0) x0 = __hip_atomic_fetch_add(M.nsplit, (unsigned long long)(parts - 1), __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-    x0 = (unsigned long long)__shfl((long long)x0, (int)(threadIdx.x & 63u & ~(KP - 1)), 64);
+    const unsigned long long x0 = wbase + excl;
     if (x0 + parts - 1 > M.xcap) {
         if (r == 0) atomicOr(M.err, ssd::ERR_MERGE);
         return;
     }
     const uint32_t row0 = M.nsamp + 1 + (uint32_t)x0;   // split row of part 1
     const uint32_t a_s = __shfl((int)a, (int)((threadIdx.x & 63u & ~(KP - 1)) + rs), 64);
-    for (uint32_t t = 1; t < parts; ++t) {
-        const uint32_t sp = a_s + (uint32_t)(((uint64_t)t * ds) / parts);   // split element's place in run rs
-        const MEnt sr = M.ent[M.rb[rs] + sp];
-        if (mine) {
-            uint32_t c, ch = NOREF;
-            uint64_t cc = 0;
-            if (r == rs) {
-                c = sp;
-                if (sr.ln <= HMASK - 8) ch = hv_pack(sr.ln, 8);
-            } else {
-                const MEnt *run = M.ent + M.rb[r];
-                uint32_t lo = a, hi = b, llo = 0, lhi = 0, vhi = 0;
-                uint64_t whi = 0;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    bool mid_less;
-                    const MEnt &rm = run[mid];
-                    uint64_t lw;
-                    uint32_t lv;
-                    const uint32_t l = cmp_at(M, rm.id, rm.st, rm.ln, sr.id, sr.st, sr.ln, min(llo, lhi), &mid_less,
-                                              &lw, &lv);
-                    if (mid_less) {
-                        lo = mid + 1;
-                        llo = l;
-                    } else {
-                        hi = mid;
-                        lhi = l;
-                        whi = lw;
-                        vhi = lv;
-                    }
-                }
-                c = lo;
-                // (below b the element at the cut was compared: hi came down to it)
-                if (c < b && lhi <= HMASK - 8) {
-                    ch = hv_pack(lhi, vhi);
-                    cc = whi;
-                }
-            }
-            const size_t q = (size_t)(row0 + t - 1) * K + r;
-            M.cuts[q] = c;
-            M.cuth[q] = ch;
-            M.cutc[q] = cc;
-        }
+    // the split elements' places in run rs; their cuts are searched by
+    // k_msplit_rows, one lane group per split row
+    for (uint32_t t = 1 + r; t < parts; t += KP) {
+        uint32_t *x = M.xd + 3 * (size_t)(x0 + t - 1);
+        x[0] = j;
+        x[1] = rs;
+        x[2] = a_s + (uint32_t)(((uint64_t)t * ds) / parts);
     }
     if (r == 0) {
         M.ja[j] = j;
@@ -413,6 +391,70 @@ __global__ void k_msplit(MergeParams M) {
             M.jb[s] = t + 1 < parts ? row0 + t : j + 1;
         }
     }
+}
+
+// The cuts of every split row: lane r of the row's group finds, inside the
+// row's job, the lower bound of the split element in run r (in run rs, the
+// split element itself), with the element's LCP with it and its characters
+// there, as the sample search does.
+__global__ void k_msplit_rows(MergeParams M) {
+    if (*M.err) return;
+    uint32_t KP = 1;
+    while (KP < M.K) KP <<= 1;
+    const uint32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t x = gt / KP, r = gt % KP;
+    const uint32_t nx = (uint32_t)min(*M.nsplit, (unsigned long long)M.xcap);
+    if (x >= nx || r >= M.K) return;
+    const uint32_t K = M.K;
+    const uint32_t j = M.xd[3 * (size_t)x], rs = M.xd[3 * (size_t)x + 1], sp = M.xd[3 * (size_t)x + 2];
+    if (j >= M.nsamp || rs >= K || sp >= M.rb[rs + 1] - M.rb[rs]) {
+        atomicOr(M.err, ssd::ERR_MERGE);
+        return;
+    }
+    const uint32_t a = M.cuts[(size_t)j * K + r];
+    const uint32_t b = (j + 1 < M.nsamp) ? M.cuts[(size_t)(j + 1) * K + r] : M.rb[r + 1] - M.rb[r];
+    if (a == SENT || b == SENT || a > b || b > M.rb[r + 1] - M.rb[r]) {
+        atomicOr(M.err, ssd::ERR_MERGE);
+        return;
+    }
+    const MEnt sr = M.ent[M.rb[rs] + sp];
+    uint32_t c, ch = NOREF;
+    uint64_t cc = 0;
+    if (r == rs) {
+        c = sp;
+        if (sr.ln <= HMASK - 8) ch = hv_pack(sr.ln, 8);
+    } else {
+        const MEnt *run = M.ent + M.rb[r];
+        uint32_t lo = a, hi = b, llo = 0, lhi = 0, vhi = 0;
+        uint64_t whi = 0;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            bool mid_less;
+            const MEnt &rm = run[mid];
+            uint64_t lw;
+            uint32_t lv;
+            const uint32_t l = cmp_at(M, rm.id, rm.st, rm.ln, sr.id, sr.st, sr.ln, min(llo, lhi), &mid_less, &lw, &lv);
+            if (mid_less) {
+                lo = mid + 1;
+                llo = l;
+            } else {
+                hi = mid;
+                lhi = l;
+                whi = lw;
+                vhi = lv;
+            }
+        }
+        c = lo;
+        // (below b the element at the cut was compared: hi came down to it)
+        if (c < b && lhi <= HMASK - 8) {
+            ch = hv_pack(lhi, vhi);
+            cc = whi;
+        }
+    }
+    const size_t q = (size_t)(M.nsamp + 1 + x) * K + r;
+    M.cuts[q] = c;
+    M.cuth[q] = ch;
+    M.cutc[q] = cc;
 }
 
 // Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run, its

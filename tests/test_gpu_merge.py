@@ -167,3 +167,47 @@ def test_merge_error_word_outlives_the_call(sorter):
     assert sorter.query_error() == 0
     assert sorter.stats()["error_bits"] == 0
     del junk
+
+
+def test_merge_full_size_long_prefixes(sorter):
+    """The merge at the benchmark's size: 8 runs (contiguous index ranges,
+    each sorted by the GPU) of 2^24 long-prefix strings, merged twice into
+    sentinel-filled outputs.  Every position is written, both merges equal
+    the full sort (element by element, permutation and LCP array), and at
+    sampled positions the order and LCP hold against the strings themselves
+    (the oracle's byte loop, at any size)."""
+    import os
+    from paper_1403_2056_amd import ssort
+    ss = W.prefixes(1 << 24, seed=2)
+    n, K = ss.n, 8
+    print(f"[merge] full size n={n} K={K}", flush=True)
+    bounds = [n * k // K for k in range(K + 1)]
+    d = ssort.strings_to_device(ss)
+    sb = torch.tensor(bounds, dtype=torch.int32).cuda()
+    p, h = sorter.sort_batched(d, sb)
+    off = torch.repeat_interleave(torch.tensor(bounds[:-1], dtype=torch.int32),
+                                  torch.tensor(np.diff(bounds), dtype=torch.int64)).cuda()
+    pg = (p + off).contiguous()
+    fp, fh = sorter.sort(d)
+    torch.cuda.synchronize()
+    fp, fh = ssort.to_numpy_u32(fp), ssort.to_numpy_u32(fh)
+    for rep in range(2):
+        m = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        hm = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        sorter.merge(d, bounds, pg, h, out_perm=m, out_lcp=hm)
+        torch.cuda.synchronize()
+        assert sorter.query_error() == 0, sorter.stats()
+        mp, mh = ssort.to_numpy_u32(m), ssort.to_numpy_u32(hm)
+        assert not np.any(mp == 0xFFFFFFFF) and not np.any(mh == 0xFFFFFFFF), rep
+        if not np.array_equal(mp, fp):
+            raise AssertionError(f"rep {rep}: perm differs from the full sort at {int(np.nonzero(mp != fp)[0][0])}")
+        if not np.array_equal(mh, fh):
+            bad = np.nonzero(mh != fh)[0]
+            raise AssertionError(f"rep {rep}: {len(bad)} LCPs differ from the full sort, first at {int(bad[0])}")
+    strs = ss.strings()
+    rng = np.random.default_rng(74)
+    for q in rng.integers(1, n, size=20000):
+        a, b = strs[int(mp[q - 1])], strs[int(mp[q])]
+        lcp = len(os.path.commonprefix([a, b]))
+        assert int(mh[q]) == lcp, q
+        assert a < b or (a == b and mp[q - 1] < mp[q]), q
