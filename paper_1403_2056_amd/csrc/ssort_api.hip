@@ -600,7 +600,8 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
         uint32_t kps = 1;
         while (kps < K) kps <<= 1;
         hipLaunchKernelGGL(ssm::k_msample, dim3((uint32_t)(((size_t)L.nsamp * kps + 63) / 64)), dim3(64), 0, s, M);
-        hipLaunchKernelGGL(ssm::k_msplit, dim3((uint32_t)(((size_t)L.nsamp * kps + 63) / 64)), dim3(64), 0, s, M);
+        hipLaunchKernelGGL(ssm::k_msplit, dim3((uint32_t)(((size_t)L.nsamp * kps + ssm::SPLIT_NT - 1) / ssm::SPLIT_NT)),
+                           dim3(ssm::SPLIT_NT), 0, s, M);
         hipLaunchKernelGGL(ssm::k_msplit_rows, dim3((uint32_t)(((size_t)L.xcap * kps + 63) / 64)), dim3(64), 0, s, M);
     }
     {

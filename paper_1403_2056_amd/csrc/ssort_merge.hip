@@ -312,8 +312,11 @@ __global__ void k_msample(MergeParams M) {
 // KP lanes per job, lane r for run r.  The job list: job j is rows (j, j+1)
 // unsplit, else (j, x_1), (x_1, x_2), ..., (x_{p-1}, j+1) with the split rows
 // x_t taken from a shared counter; row nsamp holds the run ends.
-__global__ void k_msplit(MergeParams M) {
-    if (*M.err) return;
+constexpr int SPLIT_NT = 256;   // threads per k_msplit workgroup
+// (No early exit on an earlier device error: every thread reaches the
+// workgroup's barriers, and the rows it reads are in bounds whatever they
+// hold; the merge does not run after an error.)
+__global__ __launch_bounds__(SPLIT_NT) void k_msplit(MergeParams M) {
     uint32_t KP = 1;
     while (KP < M.K) KP <<= 1;
     const uint32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -343,20 +346,33 @@ __global__ void k_msplit(MergeParams M) {
     uint32_t parts = (len + M.lcap - 1) / M.lcap;
     parts = min(parts, ds);   // split elements distinct in the longest run
     if (!live || nbad) parts = 0;   // (a bad row is reported by the merge, which checks every row)
-    // split rows for the wave's jobs with one atomic: an exclusive prefix
-    // sum of the group leaders' counts over the wave
-    const uint32_t lane = threadIdx.x & 63u;
+    // split rows for the workgroup's jobs with one atomic (one per job, or
+    // per wave, serialise by the ten thousand on the counter): an exclusive
+    // prefix sum of the group leaders' counts, per wave by shuffles, then
+    // over the waves in LDS
+    __shared__ uint32_t wsum[SPLIT_NT / 64];
+    __shared__ unsigned long long bbase;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t mycnt = (r == 0 && parts > 1) ? parts - 1 : 0u;
     uint32_t incl = mycnt;
     for (uint32_t o = 1; o < 64; o <<= 1) {
         const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
         if (lane >= o) incl += v;
     }
-    const uint32_t wtot = (uint32_t)__shfl((int)incl, 63, 64);
-    unsigned long long wbase = 0;
-    if (lane == 63 && wtot)
-        wbase = __hip_atomic_fetch_add(M.nsplit, (unsigned long long)wtot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wbase = (unsigned long long)__shfl((long long)wbase, 63, 64);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (uint32_t u = 0; u < SPLIT_NT / 64; ++u) {
+        const uint32_t t = wsum[u];
+        before += u < wv ? t : 0u;
+        total += t;
+    }
+    if (threadIdx.x == 0)
+        bbase = total ? __hip_atomic_fetch_add(M.nsplit, (unsigned long long)total, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)
+                      : 0ull;
+    __syncthreads();
+    const unsigned long long wbase = bbase + before;
     const uint32_t excl = (uint32_t)__shfl((int)(incl - mycnt), (int)(lane & ~(KP - 1)), 64);
     if (!live) return;
     if (parts <= 1) {
