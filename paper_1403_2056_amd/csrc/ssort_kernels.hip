@@ -452,8 +452,23 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
                 const uint32_t cl = B.cls[q], c0 = cl & 0xFFFF, c1 = cl >> 16;
                 const uint64_t k = B.kq[q];
                 kk[u] = k;
+                // eight, then four keys a trip: their LDS reads are issued
+                // together (one at a time, each waited for its read)
                 uint32_t r = 0;
-                for (uint32_t j = c0; j < c1; ++j) {
+                uint32_t j = c0;
+                for (; j + 8 <= c1; j += 8) {
+                    uint64_t a[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) a[t] = B.kq[j + t];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) r += (a[t] < k) | ((a[t] == k) & (j + t < q));
+                }
+                for (; j + 4 <= c1; j += 4) {
+                    const uint64_t a0 = B.kq[j], a1 = B.kq[j + 1], a2 = B.kq[j + 2], a3 = B.kq[j + 3];
+                    r += ((a0 < k) | ((a0 == k) & (j < q))) + ((a1 < k) | ((a1 == k) & (j + 1 < q))) +
+                         ((a2 < k) | ((a2 == k) & (j + 2 < q))) + ((a3 < k) | ((a3 == k) & (j + 3 < q)));
+                }
+                for (; j < c1; ++j) {
                     const uint64_t kj = B.kq[j];
                     r += (j < q ? kj <= k : kj < k) ? 1u : 0u;
                 }
