@@ -501,7 +501,7 @@ ssort_status ssort_sort_batched(ssort_ctx *ctx, const ssort_strings *flat, const
 // ---- K-way LCP-merge ----
 namespace {
 constexpr uint32_t MERGE_G = 128;   // sample spacing: n / MERGE_G jobs of about MERGE_G strings each
-constexpr uint32_t MERGE_LCAP = 128;   // longer jobs are split
+constexpr uint32_t MERGE_LCAP = 64;   // longer jobs are split
 
 struct MergeLayout {
     size_t ctl, ent, cuts, cuth, cutc, ja, jb, xd, total;
@@ -608,7 +608,18 @@ ssort_status ssort_merge(ssort_ctx *ctx, const ssort_strings *in, const uint32_t
         // the loser tree's LDS arrays sized for the smallest power of two >= K
         uint32_t kp = 2;
         while (kp < K) kp <<= 1;
-        const dim3 g((L.nsamp + ssm::MNT - 1) / ssm::MNT), b(ssm::MNT);
+        // one lane per job up to what the chip holds at once (lanes claim
+        // further jobs as they finish theirs): the merge is bound by each
+        // lane's chain of dependent loads, so every resident lane counts
+        const void *fn = kp <= 2    ? (const void *)ssm::k_mmerge<2>
+                         : kp == 4  ? (const void *)ssm::k_mmerge<4>
+                         : kp == 8  ? (const void *)ssm::k_mmerge<8>
+                         : kp == 16 ? (const void *)ssm::k_mmerge<16>
+                                    : (const void *)ssm::k_mmerge<ssm::MKMAX>;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, ssm::MNT, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+        const uint64_t want = ((uint64_t)L.nsamp + L.xcap + ssm::MNT - 1) / ssm::MNT;
+        const dim3 g((uint32_t)std::min<uint64_t>(want, (uint64_t)per_cu * (uint64_t)ctx->cus)), b(ssm::MNT);
         if (kp <= 2) hipLaunchKernelGGL(ssm::k_mmerge<2>, g, b, 0, s, M);
         else if (kp == 4) hipLaunchKernelGGL(ssm::k_mmerge<4>, g, b, 0, s, M);
         else if (kp == 8) hipLaunchKernelGGL(ssm::k_mmerge<8>, g, b, 0, s, M);

@@ -304,8 +304,9 @@ __global__ void k_msample(MergeParams M) {
 }
 
 // Jobs between consecutive samples vary in length (about exponentially
-// around g, the longest several times g), and the merge takes as long as its
-// longest job: a job longer than lcap is split into p = ceil(len / lcap)
+// around g, the longest several times g), and the merge takes about as long
+// as its lanes' share of the work plus the longest job: a job longer than
+// lcap is split into p = ceil(len / lcap)
 // parts at elements of its longest run (evenly spaced in that run's range),
 // each element's cut in every other run found by the same LCP-accelerated
 // binary search as the samples', inside the job's range.  One lane group of
@@ -474,25 +475,23 @@ __global__ void k_msplit_rows(MergeParams M) {
 }
 
 // Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run, its
-// string (index, start, length), its LCP with the winner of that game, and
-// its 8 characters at that LCP.  A loser's run does not advance while it sits
-// in the tree, so its string stays valid there: the replay reads no run
-// position from global memory, and a game that compares strings reads their
-// characters directly.  KM, a power of two >= K, sizes the arrays: 40 * KM
-// bytes per thread, so a tree sized for the launch's K (not the largest)
-// keeps more workgroups resident per CU.
+// string index, its LCP with the winner of that game, and its 8 characters at
+// that LCP; per run, the position of its element in the tree (or climbing)
+// and the end of its part of the job.  A loser's run does not advance while
+// it sits in the tree, so its element is the entry at its run's position: the
+// replay reads no run position from global memory, and a game that compares
+// strings reads both strings' entries there.  KM, a power of two >= K, sizes
+// the arrays: 28 * KM bytes per thread, so that a tree sized for the launch's
+// K (not the largest) keeps more workgroups resident per CU.
 template <int KM>
 struct MergeLDS {
-    uint64_t st[KM][MNT];   // the loser's string: start
     uint32_t y[KM][MNT];
     uint32_t yi[KM][MNT];   // string id of the loser's current element
-    uint32_t ln[KM][MNT];   // and length
     uint32_t h[KM][MNT];    // its LCP with the game's winner | valid cached characters << 24
     uint64_t c[KM][MNT];
-    uint32_t pos[KM][MNT];   // next element of each run (absolute)
+    uint32_t pos[KM][MNT];   // each run's element in the tree (absolute position)
     uint32_t end[KM][MNT];
 };
-
 
 // One game (Algorithm 2 with cached characters): the candidate (x, hx, cx)
 // against the node's loser (y, hy, cy), both with LCPs against the same
@@ -559,13 +558,15 @@ __device__ __forceinline__ int game_pre(uint32_t x, uint32_t xid, uint32_t hx, u
     return x_less ? 0 : 1;
 }
 
-// The strings' part: compare from `from` on (Algorithm 2 with the LCP found).
-__device__ __forceinline__ bool game_str(const MergeParams &M, uint32_t xid, uint64_t xs, uint32_t xl, uint32_t yid,
-                                         uint64_t ys, uint32_t yl, uint32_t from, uint32_t *lh, uint64_t *lc) {
+// The strings' part, for the elements at input positions px and py: compare
+// from `from` on (Algorithm 2 with the LCP found).
+__device__ __forceinline__ bool game_str(const MergeParams &M, uint32_t px, uint32_t py, uint32_t from, uint32_t *lh,
+                                         uint64_t *lc) {
+    const MEnt a = M.ent[px], b = M.ent[py];
     bool x_less;
     uint64_t lw;
     uint32_t lv;
-    uint32_t l = cmp_at(M, xid, xs, xl, yid, ys, yl, from, &x_less, &lw, &lv);
+    uint32_t l = cmp_at(M, a.id, a.st, a.ln, b.id, b.st, b.ln, from, &x_less, &lw, &lv);
     if (l > HMASK - 8) {   // beyond the packed LCP range: a device error, never a wrong order
         atomicOr(M.err, ssd::ERR_MERGE);
         l = HMASK - 8;
@@ -575,14 +576,15 @@ __device__ __forceinline__ bool game_str(const MergeParams &M, uint32_t xid, uin
     return x_less;
 }
 
-// A whole game: true when the candidate wins.
-__device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t xid, uint64_t xs, uint32_t xl,
-                                     uint32_t hx, uint64_t cx, uint32_t y, uint32_t yid, uint64_t ys, uint32_t yl,
-                                     uint32_t hy, uint64_t cy, uint32_t *lh, uint64_t *lc) {
+// A whole game between runs x and y (their elements at px, py): true when
+// the candidate wins.
+__device__ __forceinline__ bool game(const MergeParams &M, uint32_t x, uint32_t xid, uint32_t px, uint32_t hx,
+                                     uint64_t cx, uint32_t y, uint32_t yid, uint32_t py, uint32_t hy, uint64_t cy,
+                                     uint32_t *lh, uint64_t *lc) {
     uint32_t from = 0;
     const int d = game_pre(x, xid, hx, cx, y, yid, hy, cy, lh, lc, &from);
     if (d != 2) return d == 0;
-    return game_str(M, xid, xs, xl, yid, ys, yl, from, lh, lc);
+    return game_str(M, px, py, from, lh, lc);
 }
 
 template <int KM>
@@ -610,8 +612,8 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     // the candidate: its run x (SENT: exhausted), string, LCP with the last
     // output (and valid count) and cached characters; v: the node it plays
     // next, 0 once it has passed the root (it is the next output)
-    uint32_t x = SENT, xid = 0, xl = 0, hx = 0, v = 0;
-    uint64_t xs = 0, cx = 0;
+    uint32_t x = SENT, xid = 0, hx = 0, v = 0;
+    uint64_t cx = 0;
     bool first = true;             // the next output is its job's first
     for (;;) {
     if (v == 0) {
@@ -685,20 +687,18 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     for (uint32_t u = 1; u < KP; ++u) L.y[u][me] = WAITING;
     uint32_t wn = SENT, widn = 0, hwn = 0;   // the first winner
     for (uint32_t r = 0; r < KP; ++r) {
-        uint32_t x = SENT, xid = 0, hx = 0, xl = 0;
-        uint64_t cx = 0, xs = 0;
+        uint32_t x = SENT, xid = 0, hx = 0;
+        uint64_t cx = 0;
         if (r < K && L.pos[r][me] < L.end[r][me]) {
             const MEnt &e = M.ent[L.pos[r][me]];
             x = r;
             xid = e.id;
-            xs = e.st;
-            xl = e.ln;
             if (ref) {
                 hx = M.cuth[(size_t)ra * K + r];
                 cx = M.cutc[(size_t)ra * K + r];
             } else {
                 hx = hv_pack(0, 8);
-                cx = key_at(M.S.chars, M.S.nchars, xs, xl, 0);
+                cx = key_at(M.S.chars, M.S.nchars, e.st, e.ln, 0);
             }
         }
         bool waits = false;
@@ -707,28 +707,24 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             if (y == WAITING) {
                 L.y[v][me] = x;
                 L.yi[v][me] = xid;
-                L.st[v][me] = xs;
-                L.ln[v][me] = xl;
                 L.h[v][me] = hx;
                 L.c[v][me] = cx;
                 waits = true;
                 break;
             }
-            const uint32_t yid = L.yi[v][me], yl = L.ln[v][me];
-            const uint64_t ys = L.st[v][me];
+            const uint32_t yid = L.yi[v][me];
             const uint32_t hy = L.h[v][me];
             const uint64_t cy = L.c[v][me];
             uint32_t lh;
             uint64_t lc;
-            if (!game(M, x, xid, xs, xl, hx, cx, y, yid, ys, yl, hy, cy, &lh, &lc)) {
+            // (a string comparison only between two live players: sentinels
+            // are decided first)
+            const uint32_t px = x < K ? L.pos[x][me] : 0u, py = y < K ? L.pos[y][me] : 0u;
+            if (!game(M, x, xid, px, hx, cx, y, yid, py, hy, cy, &lh, &lc)) {
                 L.y[v][me] = x;
                 L.yi[v][me] = xid;
-                L.st[v][me] = xs;
-                L.ln[v][me] = xl;
                 x = y;
                 xid = yid;
-                xs = ys;
-                xl = yl;
                 hx = hy;
                 cx = cy;
             }
@@ -760,8 +756,6 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     if (p + 1 < L.end[run][me]) {
         const MEnt e = M.ent[p + 1];
         xid = e.id;
-        xs = e.st;
-        xl = e.ln;
         hx = hv_pack(e.h, 8);
         cx = e.c;
     } else {
@@ -786,14 +780,8 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
         if (d == 1) {
             L.y[v][me] = x;
             L.yi[v][me] = xid;
-            const uint64_t ys = L.st[v][me];
-            const uint32_t yl = L.ln[v][me];
-            L.st[v][me] = xs;
-            L.ln[v][me] = xl;
             x = y;
             xid = yid;
-            xs = ys;
-            xl = yl;
             hx = hy;
             cx = cy;
         }
@@ -803,21 +791,17 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     }
     if (stop) {
         // the game at node v compares the strings
-        const uint32_t y = L.y[v][me], yid = L.yi[v][me], yl = L.ln[v][me];
-        const uint64_t ys = L.st[v][me];
+        // (both runs live: a sentinel never needs the strings)
+        const uint32_t y = L.y[v][me], yid = L.yi[v][me];
         const uint32_t hy = L.h[v][me];
         const uint64_t cy = L.c[v][me];
         uint32_t lh;
         uint64_t lc;
-        if (!game_str(M, xid, xs, xl, yid, ys, yl, from, &lh, &lc)) {
+        if (!game_str(M, L.pos[x][me], L.pos[y][me], from, &lh, &lc)) {
             L.y[v][me] = x;
             L.yi[v][me] = xid;
-            L.st[v][me] = xs;
-            L.ln[v][me] = xl;
             x = y;
             xid = yid;
-            xs = ys;
-            xl = yl;
             hx = hy;
             cx = cy;
         }
