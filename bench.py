@@ -267,7 +267,7 @@ def bench_batched(args, embedded: bool = False):
     return out
 
 
-def bench_serve(args):
+def bench_serve(args, embedded: bool = False):
     """Serving form: a Poisson stream of jobs (sizes 2^U(4,20) strings, each
     drawn from the plain / long-prefix / suffix generators), admitted by a
     64 GB resident-memory budget with continuous batching, against the same
@@ -323,6 +323,8 @@ def bench_serve(args):
                       "strings": ntot, "budget_gb": args.budget_gb},
            "served_saturated": sat, "served_at_0.7x": lat, "one_at_a_time": one, "one_at_a_time_at_0.7x": one_lat,
            "throughput_vs_one_at_a_time": round(sat["jobs_per_s"] / mu1, 2)}
+    if embedded:
+        return out
     print(json.dumps(out), flush=True)
 
 
@@ -334,8 +336,11 @@ def main():
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true",
-                    help="plain mode: skip the batched block (4096 sets, graph launch vs one at a time)")
+                    help="plain mode: skip the batched block (4096 sets, graph launch vs one at a time) "
+                         "and the served block")
     ap.add_argument("--batched-steps", type=int, default=5, help="timed graph launches of the batched block")
+    ap.add_argument("--no-served", action="store_true",
+                    help="plain mode: skip the served block (Poisson jobs, continuous batching vs one at a time)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a device copy of this many GiB (counter scaling runs)")
     ap.add_argument("--gather-probe-m", type=int, default=0,
@@ -506,6 +511,15 @@ def main():
         ba = argparse.Namespace(**vars(args))
         ba.sets, ba.size_log2_max, ba.steps, ba.warmup = 4096, 18, args.batched_steps, 2
         out["batched"] = bench_batched(ba, embedded=True)
+    if not args.no_batched and not args.no_served:
+        # the serving form: the same Poisson job stream served with
+        # continuous batching and one job at a time
+        torch.cuda.empty_cache()
+        sa = argparse.Namespace(**vars(args))
+        sa.jobs, sa.size_log2_max, sa.budget_gb = 600, 20, 64
+        sv = bench_serve(sa, embedded=True)
+        out["served"] = {k: sv[k] for k in ("value", "unit", "config", "served_saturated", "served_at_0.7x",
+                                           "one_at_a_time", "one_at_a_time_at_0.7x", "throughput_vs_one_at_a_time")}
     print(json.dumps(out), flush=True)
 
 
