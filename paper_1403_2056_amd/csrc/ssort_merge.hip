@@ -262,9 +262,36 @@ __global__ void k_msample(MergeParams M) {
             c = pos;
             if (sr.ln <= HMASK - 8) ch = hv_pack(sr.ln, 8);   // the sample itself: its whole length, then the end
         } else {
+            // first among run r's own samples (every g-th element: few, and
+            // shared by every search of the run, so they stay in the
+            // caches), then inside the one sample interval that holds the
+            // cut; the LCPs with the bracketing elements carry over
             const MEnt *run = M.ent + M.rb[r];
-            uint32_t lo = 0, hi = M.rb[r + 1] - M.rb[r], llo = 0, lhi = 0, vhi = 0;
+            const uint32_t len = M.rb[r + 1] - M.rb[r];
+            uint32_t llo = 0, lhi = 0, vhi = 0;
             uint64_t whi = 0;
+            uint32_t slo = 0, shi = samples_below(len, M.g);
+            while (slo < shi) {
+                const uint32_t mid = (slo + shi) >> 1;
+                bool mid_less;
+                const MEnt &rm = run[(size_t)mid * M.g];
+                uint64_t lw;
+                uint32_t lv;
+                const uint32_t l = cmp_at(M, rm.id, rm.st, rm.ln, sr.id, sr.st, sr.ln, min(llo, lhi), &mid_less, &lw, &lv);
+                if (mid_less) {
+                    slo = mid + 1;
+                    llo = l;
+                } else {
+                    shi = mid;
+                    lhi = l;
+                    whi = lw;
+                    vhi = lv;
+                }
+            }
+            // slo samples are below: the elements up to sample slo - 1 are,
+            // sample slo (if any) is not
+            uint32_t lo = slo ? (slo - 1) * M.g + 1 : 0u;
+            uint32_t hi = min(slo * M.g, len);
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
                 bool mid_less;
