@@ -503,13 +503,14 @@ __global__ void k_msplit_rows(MergeParams M) {
 
 // Per-thread loser tree in LDS: node v (1..K-1) holds the loser's run, its
 // string index, its LCP with the winner of that game, and its 8 characters at
-// that LCP; per run, the position of its element in the tree (or climbing)
-// and the end of its part of the job.  A loser's run does not advance while
-// it sits in the tree, so its element is the entry at its run's position: the
-// replay reads no run position from global memory, and a game that compares
-// strings reads both strings' entries there.  KM, a power of two >= K, sizes
-// the arrays: 28 * KM bytes per thread, so that a tree sized for the launch's
-// K (not the largest) keeps more workgroups resident per CU.
+// that LCP; per run, the position of its element in the tree (or climbing).
+// A loser's run does not advance while it sits in the tree, so its element
+// is the entry at its run's position: the replay reads no run position from
+// global memory, and a game that compares strings reads both strings'
+// entries there.  The end of a run's part of the job comes from the job's
+// upper cut row (a cached read beside the next entry's).  KM, a power of two
+// >= K, sizes the arrays: 24 * KM bytes per thread, so that a tree sized for
+// the launch's K (not the largest) keeps more workgroups resident per CU.
 template <int KM>
 struct MergeLDS {
     uint32_t y[KM][MNT];
@@ -517,7 +518,6 @@ struct MergeLDS {
     uint32_t h[KM][MNT];    // its LCP with the game's winner | valid cached characters << 24
     uint64_t c[KM][MNT];
     uint32_t pos[KM][MNT];   // each run's element in the tree (absolute position)
-    uint32_t end[KM][MNT];
 };
 
 // One game (Algorithm 2 with cached characters): the candidate (x, hx, cx)
@@ -642,6 +642,9 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     uint32_t x = SENT, xid = 0, hx = 0, v = 0;
     uint64_t cx = 0;
     bool first = true;             // the next output is its job's first
+    uint32_t jrow = 0;             // the job's upper cut row
+    // end (absolute position) of run r's part of the job
+    auto run_end = [&](uint32_t r) -> uint32_t { return M.rb[r] + M.cuts[(size_t)jrow * K + r]; };
     for (;;) {
     if (v == 0) {
     if (x == SENT) {
@@ -679,13 +682,13 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
             bad |= a == SENT || b == SENT || a > b || b > M.rb[r + 1] - M.rb[r];
             if (bad) break;
             L.pos[r][me] = M.rb[r] + a;
-            L.end[r][me] = M.rb[r] + b;
             out += a;
             len += b - a;
         } else {
-            L.pos[r][me] = L.end[r][me] = 0;
+            L.pos[r][me] = 0;
         }
     }
+    jrow = rb;
     // jobs tile the output: job 0 starts at 0 and every other job where
     // another one ends, so every output position is written once
     if (bad || (j == 0 && out != 0) || out > M.n || len > M.n - out) {
@@ -710,13 +713,13 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     // in LDS and the climbing player's registers are used.
     bool ref = true;
     for (uint32_t r = 0; r < K; ++r)
-        if (L.pos[r][me] < L.end[r][me] && M.cuth[(size_t)ra * K + r] == NOREF) ref = false;
+        if (L.pos[r][me] < run_end(r) && M.cuth[(size_t)ra * K + r] == NOREF) ref = false;
     for (uint32_t u = 1; u < KP; ++u) L.y[u][me] = WAITING;
     uint32_t wn = SENT, widn = 0, hwn = 0;   // the first winner
     for (uint32_t r = 0; r < KP; ++r) {
         uint32_t x = SENT, xid = 0, hx = 0;
         uint64_t cx = 0;
-        if (r < K && L.pos[r][me] < L.end[r][me]) {
+        if (r < K && L.pos[r][me] < run_end(r)) {
             const MEnt &e = M.ent[L.pos[r][me]];
             x = r;
             xid = e.id;
@@ -780,7 +783,7 @@ __global__ __launch_bounds__(MNT) void k_mmerge(MergeParams M) {
     first = false;
     ++out;
     L.pos[run][me] = p + 1;
-    if (p + 1 < L.end[run][me]) {
+    if (p + 1 < run_end(run)) {
         const MEnt e = M.ent[p + 1];
         xid = e.id;
         hx = hv_pack(e.h, 8);
