@@ -8,9 +8,10 @@
 // sample's cut (for every run, the number of its elements below the sample)
 // comes from one LCP-accelerated binary search per run, and the cuts in
 // sample order split the merge into independent jobs (a job: for each run
-// the elements between two consecutive cuts).  One thread merges one job with
-// an LCP-aware loser tree whose nodes cache the 8 characters of their string
-// at the node's LCP (the paper caches the one distinguishing character; eight
+// the elements between two consecutive cuts); long jobs are split again at
+// elements of their longest run.  A thread merges one job at a time with an
+// LCP-aware loser tree whose nodes cache the 8 characters of their string at
+// the node's LCP (the paper caches the one distinguishing character; eight
 // fit in the 64-bit word the comparisons use), so most games are decided
 // without touching the strings.  A last pass computes the LCP across job
 // boundaries.
