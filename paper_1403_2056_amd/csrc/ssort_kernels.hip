@@ -299,6 +299,29 @@ struct BaseLDS {
     uint32_t nlist;
 };
 
+// Adds to r, for the class keys a0 at position j + T and a1 at j + T + 1,
+// whether each comes before key k at position q (qd = q - j): the borrow out
+// of a - k - [j + T < q] is 1 exactly when a < k, or a = k at an earlier
+// position.  One compare and a three-step carry chain per key (left to
+// itself the compiler emits two 64-bit compares and mask logic per key).
+template <int T>
+__device__ __forceinline__ void rank_pair(uint32_t &r, uint64_t a0, uint64_t a1, uint64_t k, int qd) {
+    uint32_t x;
+    asm("v_cmp_lt_i32_e32 vcc, %[t0], %[qd]\n\t"
+        "v_subb_co_u32_e32 %[x], vcc, %[a0l], %[kl], vcc\n\t"
+        "v_subb_co_u32_e32 %[x], vcc, %[a0h], %[kh], vcc\n\t"
+        "v_addc_co_u32_e32 %[r], vcc, 0, %[r], vcc\n\t"
+        "v_cmp_lt_i32_e32 vcc, %[t1], %[qd]\n\t"
+        "v_subb_co_u32_e32 %[x], vcc, %[a1l], %[kl], vcc\n\t"
+        "v_subb_co_u32_e32 %[x], vcc, %[a1h], %[kh], vcc\n\t"
+        "v_addc_co_u32_e32 %[r], vcc, 0, %[r], vcc"
+        : [r] "+v"(r), [x] "=&v"(x)
+        : [t0] "n"(T), [t1] "n"(T + 1), [qd] "v"(qd), [a0l] "v"((uint32_t)a0), [a0h] "v"((uint32_t)(a0 >> 32)),
+          [a1l] "v"((uint32_t)a1), [a1h] "v"((uint32_t)(a1 >> 32)), [kl] "v"((uint32_t)k),
+          [kh] "v"((uint32_t)(k >> 32))
+        : "vcc");
+}
+
 // Group accessor: group g of the chunk has global start gstart(g), size
 // gsize(g), common depth gdepth(g) and chunk-local exclusive prefix gpre(g).
 template <int C, typename G, typename Mark, typename KC>
@@ -460,13 +483,17 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
                     uint64_t a[8];
 #pragma unroll
                     for (int t = 0; t < 8; ++t) a[t] = B.kq[j + t];
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) r += (a[t] < k) | ((a[t] == k) & (j + t < q));
+                    const int qd = (int)q - (int)j;
+                    rank_pair<0>(r, a[0], a[1], k, qd);
+                    rank_pair<2>(r, a[2], a[3], k, qd);
+                    rank_pair<4>(r, a[4], a[5], k, qd);
+                    rank_pair<6>(r, a[6], a[7], k, qd);
                 }
                 for (; j + 4 <= c1; j += 4) {
                     const uint64_t a0 = B.kq[j], a1 = B.kq[j + 1], a2 = B.kq[j + 2], a3 = B.kq[j + 3];
-                    r += ((a0 < k) | ((a0 == k) & (j < q))) + ((a1 < k) | ((a1 == k) & (j + 1 < q))) +
-                         ((a2 < k) | ((a2 == k) & (j + 2 < q))) + ((a3 < k) | ((a3 == k) & (j + 3 < q)));
+                    const int qd = (int)q - (int)j;
+                    rank_pair<0>(r, a0, a1, k, qd);
+                    rank_pair<2>(r, a2, a3, k, qd);
                 }
                 for (; j < c1; ++j) {
                     const uint64_t kj = B.kq[j];
