@@ -5,8 +5,10 @@ length 10..60 plus a random suffix of length 5..80 over a 64-symbol alphabet,
 
 Prints one JSON line: strings/s over K timed sorts, the distinguishing-prefix
 rate, the roofline of the dominant kernel (the persistent worker, timed with
-HIP events on the sort's own stream) and the CPU oracle timed on the same
-input on one host core.
+HIP events on the sort's own stream), the attainable rates of the sort's two
+access patterns measured on the same GPU (a device copy, random 8-byte
+gathers), and the CPU oracle timed on the same input on all host threads and
+on one; by default also the batched and served forms.
 """
 from __future__ import annotations
 
@@ -55,6 +57,50 @@ def dist_bytes(lens_sorted: np.ndarray, lcp: np.ndarray) -> np.ndarray:
     right = np.zeros_like(h)
     right[:-1] = h[1:]
     return np.minimum(lens_sorted.astype(np.int64), 1 + np.maximum(left, right))
+
+
+def attainable_probes(torch, w_ms: float, traffic_file: dict | None) -> dict:
+    """Measured ceilings on this GPU for the sort's two access patterns: a
+    1 GiB device copy (sequential read and write) and random 8-byte gathers
+    from a 1 GiB table (torch index_select of 2^26 random indices: each gather
+    one line fill, plus the in-order index reads and word writes).  With the
+    worker's counted fetch bytes (at the copy's scale, 128 bytes per random
+    line fill), also the worker's line fills per second against the probe."""
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    nb = 1 << 30
+    a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s, e = ev(), ev()
+    s.record()
+    for _ in range(5):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * nb * 5 / (s.elapsed_time(e) / 1e3) / 1e9
+    del a, b
+    m = 1 << 26
+    table = torch.zeros(1 << 27, dtype=torch.int64, device="cuda")
+    idx = torch.randint(0, 1 << 27, (m,), dtype=torch.int64, device="cuda")
+    g = torch.index_select(table, 0, idx)
+    s, e = ev(), ev()
+    s.record()
+    for _ in range(3):
+        g = torch.index_select(table, 0, idx)
+    e.record()
+    torch.cuda.synchronize()
+    gathers = 3 * m / (s.elapsed_time(e) / 1e3)
+    del table, idx, g
+    torch.cuda.empty_cache()
+    out = {"copy_gbps": round(copy_gbps, 1), "copy_frac_of_hbm_peak": round(copy_gbps / HBM_PEAK_GBS, 4),
+           "random_gathers_per_s": round(gathers, 1)}
+    if traffic_file is not None:
+        fills = traffic_file["fetch_bytes"] / 128.0
+        rate = fills / (w_ms / 1000.0)
+        out["worker_line_fills_per_launch"] = round(fills)
+        out["worker_line_fills_per_s"] = round(rate, 1)
+        out["worker_frac_of_gather_probe"] = round(rate / gathers, 4)
+    return out
 
 
 def bench_merge(args):
@@ -341,6 +387,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5, help="timed graph launches of the batched block")
     ap.add_argument("--no-served", action="store_true",
                     help="plain mode: skip the served block (Poisson jobs, continuous batching vs one at a time)")
+    ap.add_argument("--no-probes", action="store_true",
+                    help="plain mode: skip the attainable copy and gather rates")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run a device copy of this many GiB (counter scaling runs)")
     ap.add_argument("--gather-probe-m", type=int, default=0,
@@ -443,15 +491,18 @@ def main():
     w_ms = float(np.mean(worker_ms))
     b_worker = int(np.maximum(dist - 8, 0).sum()) + 10 * int(st["strings"]) + 8 * n
     achieved = b_worker / (w_ms / 1000.0) / 1e9
-    traffic = None
+    traffic, tf_now = None, None
     if os.path.exists(TRAFFIC_FILE):
         tf = json.load(open(TRAFFIC_FILE))
         if (tf.get("source_hash") == source_hash() and args.workload == "prefixes" and n == 1 << 24
                 and sorter.tuning.as_dict() == tf.get("tuning", sorter.tuning.as_dict())):
-            traffic = tf.get("bytes_per_launch")
+            traffic, tf_now = tf.get("bytes_per_launch"), tf
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "k_worker", "avg_launch_ms": round(w_ms, 4), "algorithmic_bytes": b_worker}
+    if traffic is not None:
+        roofline["traffic_over_algorithmic"] = round(traffic / b_worker, 2)
+    probes = None if args.no_probes else attainable_probes(torch, w_ms, tf_now)
 
     cpu = None
     if not args.no_cpu:
@@ -501,6 +552,7 @@ def main():
                      "seam": round(float(np.mean(seam_ms)), 4)},
         "device_stats": st,
         "roofline": roofline,
+        "attainable": probes,
         "cpu_baseline": cpu,
     }
     if not args.no_batched:
