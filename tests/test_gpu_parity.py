@@ -113,6 +113,19 @@ def test_all_identical_large(sorter):
     assert_parity(sorter, W.from_list([b"samestring"] * 200000), "identical 200000")
 
 
+@pytest.mark.parametrize("n", [700, 40000])
+def test_largest_keys_with_ties(sorter, n):
+    """Runs of 0xFF bytes make the largest key (all 64 bits set) at many
+    depths, with equal keys at earlier and later positions of a class: the
+    base case's (key, position) order must hold at the top of the key range,
+    next to keys that differ from it only in their last byte."""
+    rng = np.random.default_rng(n)
+    tails = [b"", b"\x01", b"\xfe", b"\xff\x01", b"\xfe\xff", b"\x7f"]
+    strs = [b"\xff" * int(rng.integers(0, 41)) + tails[int(rng.integers(0, len(tails)))] for _ in range(n)]
+    strs += [strs[int(i)] for i in rng.integers(0, n, size=n // 5)]
+    assert_parity(sorter, W.from_list(strs), f"0xFF runs {len(strs)}")
+
+
 def test_long_common_prefix(sorter):
     rng = np.random.default_rng(7)
     p = b"q" * 700
