@@ -378,10 +378,8 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
         // class's first member from the class depth on (instead of one round
         // per 8 equal bytes)
         if (!first) {
-        for (uint32_t q = tid; q < M; q += NT)
-            if (q == (B.cls[q] & 0xFFFF) && B.d[B.ord[cur][q]] != DONE) B.scr[q] = 0xFFFFFFFFu;
-        if (tid == 0) B.nlist = 0;
-        __syncthreads();
+        // (each active class's running minimum at its head and the list
+        // count were reset when the classes were split)
         // first 32 bytes of every member against its class head; the pairs
         // still equal go to a list (kept where the keys go: they are gathered
         // again after the extension)
@@ -429,12 +427,13 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
             }
         }
         __syncthreads();
+        mk(PH_BEXT);
+        // the new depths: each thread writes those of the elements at its own
+        // positions, which only it reads (for their keys, below)
         for (uint32_t q = tid; q < M; q += NT) {
             const uint32_t e = B.ord[cur][q];
             if (B.d[e] != DONE) B.d[e] = B.scr[B.cls[q] & 0xFFFF];
         }
-        __syncthreads();
-        mk(PH_BEXT);
         }
         first = false;
         {
@@ -551,7 +550,14 @@ __device__ __forceinline__ void base_chunk(const Params &P, BaseLDS<C> &B, uint3
             for (uint32_t q = tid; q < M; q += NT)
                 if (q + 1 == M || B.scr[q + 1] != B.scr[q]) cend[B.scr[q]] = q + 1;
             __syncthreads();
-            for (uint32_t q = tid; q < M; q += NT) B.cls[q] = B.scr[q] | (cend[B.scr[q]] << 16);
+            // and the next round's running minimum of each active class
+            // starts at its head (only the head's thread reads that slot here)
+            for (uint32_t q = tid; q < M; q += NT) {
+                const uint32_t c0 = B.scr[q];
+                B.cls[q] = c0 | (cend[c0] << 16);
+                if (c0 == q && B.d[B.ord[cur][q]] != DONE) B.scr[q] = 0xFFFFFFFFu;
+            }
+            if (tid == 0) B.nlist = 0;
         }
         __syncthreads();
         if (tid == 0) B.any = 0;
