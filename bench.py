@@ -405,7 +405,7 @@ def main():
     ap.add_argument("--size-log2-max", type=int, default=0,
                     help="batched/serve: largest set or job size exponent (default 18 / 20)")
     ap.add_argument("--retune", action="store_true")
-    ap.add_argument("--jobs", type=int, default=600)
+    ap.add_argument("--jobs", type=int, default=1200)
     ap.add_argument("--budget-gb", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -568,7 +568,7 @@ def main():
         # continuous batching and one job at a time
         torch.cuda.empty_cache()
         sa = argparse.Namespace(**vars(args))
-        sa.jobs, sa.size_log2_max, sa.budget_gb = 600, 20, 64
+        sa.jobs, sa.size_log2_max, sa.budget_gb = 1200, 20, 64
         sv = bench_serve(sa, embedded=True)
         out["served"] = {k: sv[k] for k in ("value", "unit", "config", "served_saturated", "served_at_0.7x",
                                            "one_at_a_time", "one_at_a_time_at_0.7x", "throughput_vs_one_at_a_time")}
