@@ -84,6 +84,23 @@ def test_merge_adversarial(sorter):
             merge_parity(sorter, W.from_list(strs), 1 + i % 6, i, f"adversarial {i}")
 
 
+def test_merge_random_sweep(sorter):
+    """Seeded mixes of the adversarial kinds split into K = 1..32 runs, at
+    random or in contiguous ranges (many cut searches land in long runs of
+    equal strings or of strings that are prefixes of one another)."""
+    rng = np.random.default_rng(7300)
+    for c in range(160):
+        strs = []
+        for _ in range(int(rng.integers(1, 4))):
+            strs += adversarial(rng, int(rng.integers(1, 5000)))
+        if not strs:
+            continue
+        rng.shuffle(strs)
+        K = int(rng.integers(1, 33))
+        merge_parity(sorter, W.from_list(strs), K, int(rng.integers(0, 1 << 30)), f"sweep {c}",
+                     contiguous=bool(rng.random() < 0.3))
+
+
 def test_merge_identical_and_empty_runs(sorter):
     from paper_1403_2056_amd import ssort
     ss = W.from_list([b"same"] * 5000 + [b"x", b""] * 100)

@@ -231,6 +231,43 @@ def test_batched_small(sorter):
         assert np.array_equal(h[a:b], rh), s
 
 
+def test_batched_random_sweep():
+    """Seeded batches of 1..120 sets, a tenth of them empty, the others mixes
+    of the adversarial kinds (1..2500 strings), under random tunings: every
+    set's permutation and LCP array equal the oracle's sort of that set."""
+    from paper_1403_2056_amd import ssort
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rng = np.random.default_rng(7200)
+    sorters = {}
+    for c in range(30):
+        sets = []
+        for _ in range(int(rng.integers(1, 121))):
+            sets.append([] if rng.random() < 0.1 else adversarial(rng, int(rng.integers(1, 2500))))
+        sb = np.zeros(len(sets) + 1, dtype=np.uint32)
+        sb[1:] = np.cumsum([len(s) for s in sets])
+        if sb[-1] == 0:
+            continue
+        ss = W.from_list([x for s in sets for x in s])
+        key = (int(rng.choice([7, 63, 255])), int(rng.choice([4, 8])), int(rng.choice([16, 128, 512])))
+        if key not in sorters:
+            sorters[key] = ssort.Sorter(0, v=key[0], keys_per_thread=key[1], base_threshold=key[2])
+            sorters[key].set_wait_limit(10000)
+        s = sorters[key]
+        print(f"[batched sweep] {c}: {len(sets)} sets, n={ss.n}, tuning {key}", flush=True)
+        perm, lcp = s.sort_batched(ssort.strings_to_device(ss), torch.from_numpy(sb.view(np.int32)).cuda())
+        torch.cuda.synchronize()
+        assert s.query_error() == 0, (c, s.stats())
+        p, h = ssort.to_numpy_u32(perm), ssort.to_numpy_u32(lcp)
+        for i, strs in enumerate(sets):
+            a, b = int(sb[i]), int(sb[i + 1])
+            if a == b:
+                continue
+            rp, rh = oracle.sort(W.from_list(strs))
+            assert np.array_equal(p[a:b], rp), (c, i)
+            assert np.array_equal(h[a:b], rh), (c, i)
+
+
 def _level_one_strings(seed):
     """80000 strings behind one 8-byte key (an equality bucket above the
     second whole-GPU level's threshold of 2^16), 50000 in a range, some
