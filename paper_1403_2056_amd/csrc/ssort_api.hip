@@ -233,11 +233,11 @@ void launch_wide_level(const ssort_ctx *c, const Params &P, const Layout &L, boo
     else if (K == 4) hipLaunchKernelGGL((k_wclassify<4, false>), tiles, b, lds, s, P);
     else if (z) hipLaunchKernelGGL((k_wclassify<8, true>), tiles, b, lds, s, P);
     else hipLaunchKernelGGL((k_wclassify<8, false>), tiles, b, lds, s, P);
-    hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), b, 0, s, P, 0u, 1u << WLO);
+    launch_colscan(P, L.maxseg, 0u, 1u << WLO, s);
     if (K == 4) hipLaunchKernelGGL((k_wscatter<4, 1>), tiles, b, 0, s, P, hb);
     else hipLaunchKernelGGL((k_wscatter<8, 1>), tiles, b, 0, s, P, hb);
     hipLaunchKernelGGL(k_whist2, tiles, b, 0, s, P, hb);
-    hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), b, 0, s, P, 0u, 1u << hb);
+    launch_colscan(P, L.maxseg, 0u, 1u << hb, s);
     if (K == 4) hipLaunchKernelGGL((k_wscatter<4, 2>), tiles, b, 0, s, P, hb);
     else hipLaunchKernelGGL((k_wscatter<8, 2>), tiles, b, 0, s, P, hb);
     hipLaunchKernelGGL(k_wbounds, tiles, b, 0, s, P);
@@ -258,7 +258,7 @@ void launch_levels(const ssort_ctx *c, const Params &P, const Layout &L, bool sc
         else if (K == 4) hipLaunchKernelGGL((k_lvl_classify<4, false>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         else if (z) hipLaunchKernelGGL((k_lvl_classify<8, true>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         else hipLaunchKernelGGL((k_lvl_classify<8, false>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
-        hipLaunchKernelGGL(k_lvl_colscan, dim3(L.maxseg * CS_G), dim3(NT), 0, s, P, l, 0u);
+        launch_colscan(P, L.maxseg, l, 0u, s);
         if (K == 4) hipLaunchKernelGGL((k_lvl_scatter<4>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         else hipLaunchKernelGGL((k_lvl_scatter<8>), dim3(L.maxtiles), dim3(NT), 0, s, P, l);
         if (schedule) hipLaunchKernelGGL(k_lvl_schedule, dim3(L.maxseg), dim3(NT), 0, s, P, l);

@@ -1486,46 +1486,49 @@ __global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
 // Exclusive scan over a segment's tiles, per bucket, of the tile histograms
 // (stored tile-major: one contiguous row of counters per tile), giving every
 // (tile, bucket) pair its offset inside the bucket, and the bucket totals.  A
-// workgroup owns 16 buckets of one segment; thread t handles bucket 16g +
-// t%16 over the tile range t/16, so 16 neighbouring threads read one 64-byte
-// run of a row.
+// workgroup owns B buckets of one segment; thread t handles bucket B g + t%B
+// over the tile range t/B, so B neighbouring threads read B adjacent counters
+// of a row.  B = 16 when a level has many segments (16 counters fill a
+// 64-byte line); B = 2 for the one segment of a plain sort's first level, so
+// that 256 workgroups share its tiles instead of 32 (8192 tiles at 2^24
+// strings: 64 per thread instead of 512).
 constexpr int CS_B = 16;
-constexpr int CS_R = NT / CS_B;
-constexpr int CS_G = NBPAD / CS_B;   // bucket groups per segment
 // nbw > 0: every segment has nbw columns (the digits of a wide level's
 // distribution passes), else its splitters' bucket count.
+template <int B>
 __global__ __launch_bounds__(NT) void k_lvl_colscan(Params P, uint32_t l, uint32_t nbw) {
-    __shared__ uint32_t part[CS_R][CS_B];
-    const uint32_t seg = blockIdx.x / CS_G, grp = blockIdx.x % CS_G;
+    constexpr int R = NT / B, G = NBPAD / B;
+    __shared__ uint32_t part[R][B];
+    const uint32_t seg = blockIdx.x / G, grp = blockIdx.x % G;
     if (P.ctl->error || seg >= lvl_count(P, l, 0)) return;
     const LvlSeg g = P.lseg[l][seg];
     const uint32_t nb = nbw ? nbw : uni(P.lsplit[l][seg].nb);
-    if (grp * CS_B >= nb) return;
-    const uint32_t b = grp * CS_B + (threadIdx.x % CS_B);
-    const uint32_t r = threadIdx.x / CS_B;
+    if (grp * B >= nb) return;
+    const uint32_t b = grp * B + (threadIdx.x % B);
+    const uint32_t r = threadIdx.x / B;
     const uint32_t T = g.ntile;
-    const uint32_t per = (T + CS_R - 1) / CS_R;
+    const uint32_t per = (T + R - 1) / R;
     const uint32_t lo = g.tile0 + min(T, r * per), hi = g.tile0 + min(T, r * per + per);
     uint32_t s = 0;
     if (b < nb) {
 #pragma unroll 8
         for (uint32_t i = lo; i < hi; ++i) s += P.hist[(size_t)i * NBPAD + b];
     }
-    part[r][threadIdx.x % CS_B] = s;
+    part[r][threadIdx.x % B] = s;
     __syncthreads();
-    if (threadIdx.x < CS_B) {
+    if (threadIdx.x < B) {
         uint32_t run = 0;
-        for (int k = 0; k < CS_R; ++k) {
+        for (int k = 0; k < R; ++k) {
             const uint32_t x = part[k][threadIdx.x];
             part[k][threadIdx.x] = run;
             run += x;
         }
-        const uint32_t bb = grp * CS_B + threadIdx.x;
+        const uint32_t bb = grp * B + threadIdx.x;
         if (bb < nb) P.ltot[l][(size_t)seg * NBPAD + bb] = run;
     }
     __syncthreads();
     if (b < nb) {
-        uint32_t run = part[r][threadIdx.x % CS_B];
+        uint32_t run = part[r][threadIdx.x % B];
         for (uint32_t i = lo; i < hi; ++i) {
             uint32_t *c = &P.hist[(size_t)i * NBPAD + b];
             const uint32_t x = *c;
@@ -1533,6 +1536,16 @@ __global__ __launch_bounds__(NT) void k_lvl_colscan(Params P, uint32_t l, uint32
             run += x;
         }
     }
+}
+
+// Column scan of level l: one workgroup per B buckets of every segment the
+// level can hold, or, for the single first-level segment of a plain sort,
+// 256 workgroups of 2 buckets.
+inline void launch_colscan(const Params &P, uint32_t maxseg, uint32_t l, uint32_t nbw, hipStream_t s) {
+    if (l == 0 && !P.set_begin)
+        hipLaunchKernelGGL(k_lvl_colscan<2>, dim3(NBPAD / 2), dim3(NT), 0, s, P, l, nbw);
+    else
+        hipLaunchKernelGGL(k_lvl_colscan<CS_B>, dim3(maxseg * (NBPAD / CS_B)), dim3(NT), 0, s, P, l, nbw);
 }
 
 template <int K>
