@@ -1490,8 +1490,8 @@ __global__ __launch_bounds__(NT) void k_lvl_classify(Params P, uint32_t l) {
 // over the tile range t/B, so B neighbouring threads read B adjacent counters
 // of a row.  B = 16 when a level has many segments (16 counters fill a
 // 64-byte line); B = 2 for the one segment of a plain sort's first level, so
-// that 256 workgroups share its tiles instead of 32 (8192 tiles at 2^24
-// strings: 64 per thread instead of 512).
+// that 256 workgroups share its tiles instead of 32 (4096 tiles at 2^24
+// strings: 32 per thread instead of 256).
 constexpr int CS_B = 16;
 // nbw > 0: every segment has nbw columns (the digits of a wide level's
 // distribution passes), else its splitters' bucket count.
